@@ -1,0 +1,204 @@
+"""Seeded synthetic LQT problem generators (inputs only, no solver arithmetic).
+
+This module is shared by the tests, the benchmark and the CPU oracle's
+callers.  It holds no step of the method: it only draws problem data of the
+shapes and distributions of the workloads below and packs them into
+``LQTProblem``.  It imports nothing from the rest of the package.
+
+Problem (Section II-B of the paper): x_{k+1} = F_k x_k + c_k + L_k u_k with
+running cost 1/2 (H_k x_k - r_k)^T X_k (H_k x_k - r_k) + 1/2 u_k^T U_k u_k for
+k = 0..T-1 and terminal cost 1/2 (H_T x_T - r_T)^T X_T (H_T x_T - r_T).
+
+Workloads (every generator draws from numpy PCG64 seeded with
+SeedSequence([2104, workload_id, instance_id]); draw order is fixed below):
+
+* ``tracking_problem`` (workloads 0 and 1): n x n dynamics F = I + 0.1 G,
+  G ~ N(0, 1/n), rescaled to spectral radius rho (0.99); L ~ N(0, 1) (n x m);
+  c = 0; H = H_T = I; X = 10 I, U = 0.1 I, X_T = 10 I; reference
+  r_{k,i} = sin(2 pi k / 200 + phi_i) with phi ~ U[0, 2 pi); x_0 ~ N(0, I).
+* ``batched_problems`` (workload 2): 4096 instances, T log-uniform on
+  [256, 16384], n uniform on {4, 8, 16}, m = n / 2, F and L as above,
+  X = diag(U[1, 10]), U = diag(U[0.01, 1]), X_T = X, random-walk reference
+  r_0 ~ N(0, I), r_{k+1} = r_k + N(0, 0.1^2 I), x_0 ~ N(0, I).
+* ``dense_problems`` (workload 3): 64 instances, n = 64, m = 32, T = 8192,
+  F with spectral radius 0.98, L ~ N(0, 1), X = W W^T + 0.1 I with
+  W ~ N(0, 1/n), U = W' W'^T + 0.1 I with W' ~ N(0, 1/m), X_T = X,
+  random-walk reference.
+* ``serving_requests`` (workload 4): Poisson arrivals at a given rate;
+  n uniform on {4..32}, m = ceil(n / 2), T log-uniform on [64, 65536], data as
+  workload 2.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+BASE_SEED = 2104
+
+PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
+
+
+@dataclasses.dataclass
+class LQTProblem:
+    """One LQT instance.  Arrays are float64, row-major.
+
+    A matrix whose ``PS_*`` bit is set in ``per_step`` carries a leading time
+    axis of length T; otherwise one matrix serves every step.  ``r`` is always
+    per step ([T][p]); ``rT`` is the terminal reference ([pT])."""
+    n: int
+    m: int
+    p: int
+    pT: int
+    T: int
+    per_step: int
+    F: np.ndarray
+    c: Optional[np.ndarray]
+    L: np.ndarray
+    H: np.ndarray
+    X: np.ndarray
+    U: np.ndarray
+    r: np.ndarray
+    HT: np.ndarray
+    XT: np.ndarray
+    rT: np.ndarray
+    x0: np.ndarray
+
+    @property
+    def steps(self) -> int:
+        return self.T
+
+
+def _rng(workload: int, instance: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, workload, instance])))
+
+
+def _dynamics(rng: np.random.Generator, n: int, m: int, rho: float):
+    """F = I + 0.1 G rescaled to spectral radius rho; L ~ N(0, 1)."""
+    G = rng.normal(0.0, 1.0 / math.sqrt(n), size=(n, n))
+    F0 = np.eye(n) + 0.1 * G
+    F = F0 * (rho / np.max(np.abs(np.linalg.eigvals(F0))))
+    L = rng.normal(0.0, 1.0, size=(n, m))
+    return np.ascontiguousarray(F), np.ascontiguousarray(L)
+
+
+def tracking_problem(n: int = 4, m: int = 2, T: int = 1000, workload: int = 0,
+                     instance: int = 0, rho: float = 0.99) -> LQTProblem:
+    """Sinusoidal-reference tracking problem (workloads 0 and 1)."""
+    rng = _rng(workload, instance)
+    F, L = _dynamics(rng, n, m, rho)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    k = np.arange(T + 1, dtype=np.float64)[:, None]
+    rr = np.sin(2.0 * math.pi * k / 200.0 + phi[None, :])
+    x0 = rng.normal(0.0, 1.0, size=n)
+    eye = np.eye(n)
+    return LQTProblem(n=n, m=m, p=n, pT=n, T=T, per_step=0, F=F, c=None, L=L,
+                      H=eye.copy(), X=10.0 * eye, U=0.1 * np.eye(m),
+                      r=np.ascontiguousarray(rr[:T]), HT=eye.copy(), XT=10.0 * eye,
+                      rT=np.ascontiguousarray(rr[T]), x0=x0)
+
+
+def _random_walk(rng, T, p, sigma=0.1):
+    r0 = rng.normal(0.0, 1.0, size=(1, p))
+    steps = rng.normal(0.0, sigma, size=(T, p))
+    return np.concatenate([r0, r0 + np.cumsum(steps, axis=0)], axis=0)
+
+
+def diag_problem(n: int, m: int, T: int, workload: int, instance: int) -> LQTProblem:
+    """Workload-2 style instance: diagonal costs, random-walk reference."""
+    rng = _rng(workload, instance)
+    F, L = _dynamics(rng, n, m, 0.99)
+    q = rng.uniform(1.0, 10.0, size=n)
+    ru = rng.uniform(0.01, 1.0, size=m)
+    rr = _random_walk(rng, T, n)
+    x0 = rng.normal(0.0, 1.0, size=n)
+    Q = np.diag(q)
+    return LQTProblem(n=n, m=m, p=n, pT=n, T=T, per_step=0, F=F, c=None, L=L,
+                      H=np.eye(n), X=Q, U=np.diag(ru), r=np.ascontiguousarray(rr[:T]),
+                      HT=np.eye(n), XT=Q.copy(), rT=np.ascontiguousarray(rr[T]), x0=x0)
+
+
+def batched_shapes(count: int = 4096, workload: int = 2):
+    """(n, T) for each instance of the uneven batch, drawn before the data."""
+    rng = _rng(workload, 1 << 30)
+    Ts = np.rint(np.exp(rng.uniform(math.log(256), math.log(16384), size=count))).astype(np.int64)
+    ns = rng.choice(np.array([4, 8, 16]), size=count)
+    return [(int(n), int(t)) for n, t in zip(ns, Ts)]
+
+
+def batched_problems(count: int = 4096, workload: int = 2):
+    return [diag_problem(n, n // 2, T, workload, i) for i, (n, T) in enumerate(batched_shapes(count, workload))]
+
+
+def dense_problem(n: int = 64, m: int = 32, T: int = 8192, workload: int = 3, instance: int = 0) -> LQTProblem:
+    """Workload-3 instance: dense SPD costs, spectral radius 0.98."""
+    rng = _rng(workload, instance)
+    F, L = _dynamics(rng, n, m, 0.98)
+    W = rng.normal(0.0, 1.0 / math.sqrt(n), size=(n, n))
+    Wu = rng.normal(0.0, 1.0 / math.sqrt(m), size=(m, m))
+    Q = W @ W.T + 0.1 * np.eye(n)
+    R = Wu @ Wu.T + 0.1 * np.eye(m)
+    Q = 0.5 * (Q + Q.T)
+    R = 0.5 * (R + R.T)
+    rr = _random_walk(rng, T, n)
+    x0 = rng.normal(0.0, 1.0, size=n)
+    return LQTProblem(n=n, m=m, p=n, pT=n, T=T, per_step=0, F=F, c=None, L=L,
+                      H=np.eye(n), X=Q, U=R, r=np.ascontiguousarray(rr[:T]),
+                      HT=np.eye(n), XT=Q.copy(), rT=np.ascontiguousarray(rr[T]), x0=x0)
+
+
+def serving_requests(rate_hz: float = 2000.0, seconds: float = 60.0, workload: int = 4):
+    """Arrival times (s) and (n, m, T) of the request stream (data drawn lazily
+    with ``diag_problem(n, m, T, workload, i)``)."""
+    rng = _rng(workload, 1 << 30)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= seconds:
+            break
+        n = int(rng.integers(4, 33))
+        T = int(round(math.exp(rng.uniform(math.log(64), math.log(65536)))))
+        out.append((t, n, (n + 1) // 2, T))
+    return out
+
+
+def random_problem(n: int, m: int, T: int, seed: int, p: Optional[int] = None, pT: Optional[int] = None,
+                   per_step: int = 0, with_c: bool = True, scale: float = 1.0) -> LQTProblem:
+    """Fully random instance for edge-case and parity tests: general H (p x n),
+    SPD X and U, non-zero offsets c, optional per-step matrices."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, 99, seed])))
+    p = n if p is None else p
+    pT = n if pT is None else pT
+
+    def mat(shape_one, bit, fn):
+        if per_step & bit:
+            return np.ascontiguousarray(np.stack([fn() for _ in range(T)]))
+        return np.ascontiguousarray(fn())
+
+    def spd(k, lo):
+        W = rng.normal(0.0, 1.0 / math.sqrt(k), size=(k, k))
+        A = W @ W.T + lo * np.eye(k)
+        return 0.5 * (A + A.T)
+
+    def dyn():
+        G = rng.normal(0.0, 1.0 / math.sqrt(n), size=(n, n))
+        F0 = np.eye(n) + 0.3 * G
+        return F0 * (scale / max(1e-12, np.max(np.abs(np.linalg.eigvals(F0)))))
+
+    F = mat((n, n), PS_F, dyn)
+    c = mat((n,), PS_c, lambda: rng.normal(0.0, 0.3, size=n)) if with_c else None
+    L = mat((n, m), PS_L, lambda: rng.normal(0.0, 1.0, size=(n, m)))
+    H = mat((p, n), PS_H, lambda: rng.normal(0.0, 1.0, size=(p, n)))
+    X = mat((p, p), PS_X, lambda: spd(p, 0.5))
+    U = mat((m, m), PS_U, lambda: spd(m, 0.2))
+    r = rng.normal(0.0, 1.0, size=(T, p))
+    HT = rng.normal(0.0, 1.0, size=(pT, n))
+    XT = spd(pT, 0.5)
+    rT = rng.normal(0.0, 1.0, size=pT)
+    x0 = rng.normal(0.0, 1.0, size=n)
+    if not with_c:
+        per_step &= ~PS_c
+    return LQTProblem(n=n, m=m, p=p, pT=pT, T=T, per_step=per_step, F=F, c=c, L=L, H=H, X=X, U=U,
+                      r=r, HT=HT, XT=XT, rT=rT, x0=x0)
