@@ -1,0 +1,170 @@
+/*
+ * lqt.h -- C ABI of the MI355X (gfx950) linear-quadratic tracker solver.
+ *
+ * The solver computes, for each LQT instance, the value functions (S_k, v_k),
+ * the control gains (K_k, d_k), the optimal trajectory x_k and the optimal
+ * controls u_k with the temporal parallelisation of Sarkka & Garcia-Fernandez,
+ * "Temporal Parallelisation of Dynamic Programming and Linear Quadratic
+ * Control" (arXiv 2104.03186):
+ *
+ *   - problem (Section II-B): x_{k+1} = F_k x_k + c_k + L_k u_k, running cost
+ *     1/2 (H_k x_k - r_k)^T X_k (H_k x_k - r_k) + 1/2 u_k^T U_k u_k for
+ *     k = 0..T-1, terminal cost 1/2 (H_T x_T - r_T)^T X_T (H_T x_T - r_T);
+ *     X_k symmetric positive semi-definite, U_k symmetric positive definite;
+ *   - value function V_k(x) = const + 1/2 x^T S_k x - v_k^T x (Section II-B);
+ *   - control law u_k = -K_k x_k + d_k with
+ *     K_k = (L_k^T S_{k+1} L_k + U_k)^{-1} L_k^T S_{k+1} F_k and
+ *     d_k = (L_k^T S_{k+1} L_k + U_k)^{-1} L_k^T (v_{k+1} - S_{k+1} c_k),
+ *     i.e. d_k = K^v_k v_{k+1} - K^c_k c_k of the control law in Section II-B;
+ *   - S_k, v_k come from a reverse associative scan over the one-step elements
+ *     (A, b, C, eta, J) of Section IV-B with the combination rule of
+ *     Section IV-A; x_k comes from a forward scan over the closed-loop affine
+ *     maps x_{k+1} = (F_k - L_k K_k) x_k + c_k + L_k d_k (Section IV-C,
+ *     Method 1).
+ *
+ * Memory: every array pointer inside lqt_problem and lqt_outputs is a DEVICE
+ * pointer on the plan's device, row-major and contiguous.  The caller owns all
+ * input and output buffers; they must stay valid until the work that reads or
+ * writes them has completed (stream-ordered for lqt_solve; until lqt_poll
+ * returns something other than LQT_EAGAIN for lqt_submit).  The library owns
+ * its workspace and frees it in lqt_destroy.
+ *
+ * Errors: every entry point returns an lqt_status and never throws.  Argument
+ * errors are reported synchronously (LQT_EINVAL) before any work is enqueued.
+ * Numerical failures are reported per instance through lqt_outputs.status;
+ * a failing instance never alters the outputs of other instances.
+ * lqt_last_error returns a human-readable description of the last synchronous
+ * error of a plan.
+ *
+ * Thread safety: a plan may be used by one host thread at a time.
+ */
+#ifndef LQT_H
+#define LQT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LQT_OK = 0,
+    LQT_EINVAL = 1,      /* invalid argument (dimension, pointer, horizon)          */
+    LQT_ENOMEM = 2,      /* device memory or the plan's memory budget is exhausted */
+    LQT_ENOTPD = 3,      /* U_k or L_k^T S_{k+1} L_k + U_k not positive definite   */
+    LQT_ENONFINITE = 4,  /* a non-finite value appeared in the solution            */
+    LQT_EAGAIN = 5,      /* lqt_poll: the request has not completed yet            */
+    LQT_EBUSY = 6,       /* lqt_submit: the in-flight queue is full                */
+    LQT_EHIP = 7,        /* a HIP runtime call failed                              */
+    LQT_ENOTSUP = 8      /* a dimension or precision this build does not provide   */
+} lqt_status;
+
+typedef enum {
+    LQT_PREC_FP64 = 0,   /* all arithmetic and all outputs in IEEE double          */
+    LQT_PREC_MIXED = 1   /* outputs in float; precision-sensitive chains in double */
+} lqt_precision;
+
+/* Bits of lqt_problem.per_step: a set bit means the matrix has a leading time
+ * axis of length T (one matrix per step k = 0..T-1); a clear bit means one
+ * matrix serves every step. */
+enum {
+    LQT_PS_F = 1, LQT_PS_c = 2, LQT_PS_L = 4, LQT_PS_H = 8, LQT_PS_X = 16, LQT_PS_U = 32
+};
+
+/* One LQT instance (Section II-B).  n = nx states, m = nu controls,
+ * p = ny tracked outputs at steps 0..T-1, pT = nyT tracked outputs at T. */
+typedef struct {
+    int32_t nx, nu, ny, nyT;
+    int64_t T;            /* number of control steps, T >= 1; states x_0..x_T     */
+    uint32_t per_step;    /* LQT_PS_* bits                                          */
+    const double *F;      /* [n][n]   or [T][n][n]                                  */
+    const double *c;      /* [n]      or [T][n]; NULL means c_k = 0                 */
+    const double *L;      /* [n][m]   or [T][n][m]                                  */
+    const double *H;      /* [p][n]   or [T][p][n]                                  */
+    const double *X;      /* [p][p]   or [T][p][p], symmetric PSD                   */
+    const double *U;      /* [m][m]   or [T][m][m], symmetric PD                    */
+    const double *r;      /* [T][p]   reference r_0..r_{T-1}                        */
+    const double *HT;     /* [pT][n]  terminal output matrix                        */
+    const double *XT;     /* [pT][pT] terminal weight, symmetric PSD                */
+    const double *rT;     /* [pT]     terminal reference r_T                        */
+    const double *x0;     /* [n]      initial state                                 */
+} lqt_problem;
+
+/* Outputs of one instance.  Element type is double for LQT_PREC_FP64 and
+ * float for LQT_PREC_MIXED.  S and v may be NULL (not written).  K and d may
+ * be NULL only when x and u are also NULL.  x and u may be NULL together
+ * (the forward pass is then skipped). */
+typedef struct {
+    void *S;              /* [T+1][n][n] value-function matrices S_0..S_T           */
+    void *v;              /* [T+1][n]    value-function vectors  v_0..v_T           */
+    void *K;              /* [T][m][n]   feedback gains K_0..K_{T-1}                */
+    void *d;              /* [T][m]      feed-forward terms d_0..d_{T-1}            */
+    void *x;              /* [T+1][n]    optimal states x_0..x_T                    */
+    void *u;              /* [T][m]      optimal controls u_0..u_{T-1}              */
+    int32_t *status;      /* optional device int32: the instance's lqt_status       */
+} lqt_outputs;
+
+typedef struct {
+    int32_t device;           /* HIP device ordinal                                 */
+    int32_t max_nx, max_nu;   /* largest dimensions the plan will accept            */
+    lqt_precision prec;
+    size_t hbm_budget_bytes;  /* cap on library-owned device memory (0: no cap)     */
+    int64_t max_steps;        /* workspace is pre-sized for this many total steps   */
+    int32_t max_inflight;     /* lqt_submit queue depth (0: default)                */
+} lqt_plan_desc;
+
+typedef struct lqt_plan_s *lqt_plan_t;
+
+/* Create a plan: validates the descriptor, selects the device, allocates the
+ * workspace for desc->max_steps steps.  On success *out receives the plan. */
+lqt_status lqt_plan(const lqt_plan_desc *desc, lqt_plan_t *out);
+
+/* Solve `count` independent instances, enqueued on `stream` (a hipStream_t;
+ * NULL is the default stream).  Stream-ordered and asynchronous: returns once
+ * the work is enqueued.  probs[i] is solved into outs[i].  Synchronous
+ * argument errors return LQT_EINVAL/LQT_ENOTSUP/LQT_ENOMEM with nothing
+ * enqueued.  The workspace grows (synchronously) when a call needs more than
+ * it holds. */
+lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
+                     int32_t count, void *stream);
+
+/* Serving interface: admit one instance for asynchronous solution on the
+ * plan's internal stream.  Returns LQT_EBUSY when the queue is full and
+ * LQT_ENOMEM when the request can never fit the memory budget.  *ticket
+ * identifies the request for lqt_poll. */
+lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem *prob, const lqt_outputs *out,
+                      uint64_t *ticket);
+
+/* LQT_EAGAIN while the request is in flight; afterwards the instance's
+ * status (LQT_OK on success).  A ticket may be polled to completion once. */
+lqt_status lqt_poll(lqt_plan_t plan, uint64_t ticket);
+
+/* Wait for all work of the plan, then release it and its workspace. */
+lqt_status lqt_destroy(lqt_plan_t plan);
+
+/* Per-kernel timing (diagnostics, tracing).  While enabled, every kernel the
+ * plan launches is bracketed by HIP events recorded on the launch stream, so
+ * the device timeline of each kernel can be read back.  Disabled by default. */
+typedef struct {
+    const char *name;     /* kernel (stage) name, owned by the library           */
+    int64_t launches;     /* launches accumulated since the last read            */
+    double total_ms;      /* summed device time of those launches                */
+} lqt_stage_time;
+
+lqt_status lqt_profile_enable(lqt_plan_t plan, int32_t enable);
+
+/* Waits for the recorded events, writes up to `max` per-stage totals (in
+ * first-launch order) into out, clears the accumulators and returns the
+ * number of stages (negative lqt_status on failure). */
+int32_t lqt_profile_read(lqt_plan_t plan, lqt_stage_time *out, int32_t max);
+
+/* Description of the last synchronous error of the plan ("" if none).
+ * The string is owned by the plan.  NULL plan: the last plan-creation error. */
+const char *lqt_last_error(lqt_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQT_H */

@@ -1,0 +1,94 @@
+"""ctypes binding of the C ABI declared in include/lqt.h (marshalling only).
+
+Loads ``liblqt.so`` from this package directory.  There is no fallback: when
+the library is missing or cannot be loaded every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblqt.so")
+
+# lqt_status
+OK, EINVAL, ENOMEM, ENOTPD, ENONFINITE, EAGAIN, EBUSY, EHIP, ENOTSUP = range(9)
+STATUS_NAMES = {OK: "LQT_OK", EINVAL: "LQT_EINVAL", ENOMEM: "LQT_ENOMEM", ENOTPD: "LQT_ENOTPD",
+                ENONFINITE: "LQT_ENONFINITE", EAGAIN: "LQT_EAGAIN", EBUSY: "LQT_EBUSY", EHIP: "LQT_EHIP",
+                ENOTSUP: "LQT_ENOTSUP"}
+PREC_FP64, PREC_MIXED = 0, 1
+PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
+
+EXPORTED = ("lqt_plan", "lqt_solve", "lqt_submit", "lqt_poll", "lqt_destroy", "lqt_profile_enable",
+            "lqt_profile_read", "lqt_last_error")
+
+_vp = ctypes.c_void_p
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("ny", ctypes.c_int32), ("nyT", ctypes.c_int32),
+                ("T", ctypes.c_int64), ("per_step", ctypes.c_uint32),
+                ("F", _vp), ("c", _vp), ("L", _vp), ("H", _vp), ("X", _vp), ("U", _vp), ("r", _vp),
+                ("HT", _vp), ("XT", _vp), ("rT", _vp), ("x0", _vp)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("S", _vp), ("v", _vp), ("K", _vp), ("d", _vp), ("x", _vp), ("u", _vp), ("status", _vp)]
+
+
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_nx", ctypes.c_int32), ("max_nu", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t), ("max_steps", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int32)]
+
+
+_lib = None
+
+
+class LQTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    """Load liblqt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is missing: build it with "
+                          "`python -m paper_2104_03186_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.lqt_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(_vp)]
+    lib.lqt_plan.restype = ctypes.c_int
+    lib.lqt_solve.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.c_int32, _vp]
+    lib.lqt_solve.restype = ctypes.c_int
+    lib.lqt_submit.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.POINTER(ctypes.c_uint64)]
+    lib.lqt_submit.restype = ctypes.c_int
+    lib.lqt_poll.argtypes = [_vp, ctypes.c_uint64]
+    lib.lqt_poll.restype = ctypes.c_int
+    lib.lqt_destroy.argtypes = [_vp]
+    lib.lqt_destroy.restype = ctypes.c_int
+    lib.lqt_profile_enable.argtypes = [_vp, ctypes.c_int32]
+    lib.lqt_profile_enable.restype = ctypes.c_int
+    lib.lqt_profile_read.argtypes = [_vp, ctypes.POINTER(StageTime), ctypes.c_int32]
+    lib.lqt_profile_read.restype = ctypes.c_int32
+    lib.lqt_last_error.argtypes = [_vp]
+    lib.lqt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error(plan) -> str:
+    s = load().lqt_last_error(plan)
+    return s.decode() if s else ""
+
+
+def check(code: int, plan=None):
+    if code != OK:
+        raise LQTError(code, last_error(plan))

@@ -1,0 +1,151 @@
+"""Python front end of the HIP LQT solver (argument marshalling only).
+
+PyTorch provides device memory and streams; every arithmetic step runs in the
+HIP kernels of liblqt.so through the C ABI of include/lqt.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+FAMILIES = ("S", "v", "K", "d", "x", "u")
+_PREC = {"fp64": _lib.PREC_FP64, "mixed": _lib.PREC_MIXED}
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class DeviceProblem:
+    """An LQT instance resident in device memory (float64 tensors)."""
+
+    FIELDS = ("F", "c", "L", "H", "X", "U", "r", "HT", "XT", "rT", "x0")
+
+    def __init__(self, prob, device="cuda:0"):
+        self.n, self.m, self.p, self.pT = int(prob.n), int(prob.m), int(prob.p), int(prob.pT)
+        self.T, self.per_step = int(prob.T), int(prob.per_step)
+        self.t = {}
+        for f in self.FIELDS:
+            a = getattr(prob, f)
+            self.t[f] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+    def struct(self) -> _lib.Problem:
+        s = _lib.Problem()
+        s.nx, s.nu, s.ny, s.nyT, s.T, s.per_step = self.n, self.m, self.p, self.pT, self.T, self.per_step
+        for f in self.FIELDS:
+            setattr(s, f, _ptr(self.t[f]))
+        return s
+
+
+class DeviceOutputs:
+    """Output buffers of one instance.  ``want`` lists the families to produce
+    (the others are passed as NULL)."""
+
+    def __init__(self, n: int, m: int, T: int, device="cuda:0", dtype=torch.float64,
+                 want: Iterable[str] = FAMILIES, status: bool = True):
+        want = set(want)
+        shapes = {"S": (T + 1, n, n), "v": (T + 1, n), "K": (T, m, n), "d": (T, m), "x": (T + 1, n), "u": (T, m)}
+        self.t: Dict[str, Optional[torch.Tensor]] = {
+            k: (torch.empty(shapes[k], dtype=dtype, device=device) if k in want else None) for k in FAMILIES}
+        self.status = torch.full((1,), -1, dtype=torch.int32, device=device) if status else None
+
+    def struct(self) -> _lib.Outputs:
+        s = _lib.Outputs()
+        for k in FAMILIES:
+            setattr(s, k, _ptr(self.t[k]))
+        s.status = _ptr(self.status)
+        return s
+
+    def host(self) -> Dict[str, np.ndarray]:
+        return {k: v.double().cpu().numpy() for k, v in self.t.items() if v is not None}
+
+
+class Plan:
+    """Owns an lqt_plan_t (workspace on one device)."""
+
+    def __init__(self, max_nx: int, max_nu: int, prec: str = "fp64", device: int = 0, max_steps: int = 0,
+                 hbm_budget_bytes: int = 0, max_inflight: int = 0):
+        lib = _lib.load()
+        d = _lib.PlanDesc(device=device, max_nx=max_nx, max_nu=max_nu, prec=_PREC[prec],
+                          hbm_budget_bytes=hbm_budget_bytes, max_steps=max_steps, max_inflight=max_inflight)
+        h = ctypes.c_void_p()
+        _lib.check(lib.lqt_plan(ctypes.byref(d), ctypes.byref(h)), None)
+        self._h = h
+        self.device = device
+        self.prec = prec
+
+    @property
+    def handle(self):
+        return self._h
+
+    def solve(self, probs: Sequence[DeviceProblem], outs: Sequence[DeviceOutputs], stream=None) -> None:
+        """Enqueue the solve of every instance on ``stream`` (default: torch's
+        current stream).  Asynchronous."""
+        if len(probs) != len(outs):
+            raise ValueError("probs and outs differ in length")
+        n = len(probs)
+        P = (_lib.Problem * max(n, 1))(*[p.struct() for p in probs])
+        O = (_lib.Outputs * max(n, 1))(*[o.struct() for o in outs])
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        _lib.check(_lib.load().lqt_solve(self._h, P, O, n, sp), self._h)
+
+    def submit(self, prob: DeviceProblem, out: DeviceOutputs) -> int:
+        t = ctypes.c_uint64()
+        ps, os_ = prob.struct(), out.struct()
+        _lib.check(_lib.load().lqt_submit(self._h, ctypes.byref(ps), ctypes.byref(os_), ctypes.byref(t)), self._h)
+        return int(t.value)
+
+    def poll(self, ticket: int) -> Optional[int]:
+        """None while in flight, else the instance status (0 = LQT_OK)."""
+        rc = _lib.load().lqt_poll(self._h, ticket)
+        if rc == _lib.EAGAIN:
+            return None
+        if rc == _lib.EINVAL or rc == _lib.EHIP:
+            raise _lib.LQTError(rc, _lib.last_error(self._h))
+        return rc
+
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every kernel launch with HIP events (see profile_read)."""
+        _lib.check(_lib.load().lqt_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self) -> Dict[str, tuple]:
+        """{stage: (launches, total_ms)} since the last read (synchronises)."""
+        buf = (_lib.StageTime * 64)()
+        n = _lib.load().lqt_profile_read(self._h, buf, 64)
+        if n < 0:
+            raise _lib.LQTError(-n, _lib.last_error(self._h))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n)}
+
+    def close(self):
+        if self._h:
+            _lib.load().lqt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_host(prob, prec: str = "fp64", device: int = 0) -> Dict[str, np.ndarray]:
+    """Convenience: copy one host problem to the device, solve, copy back."""
+    dev = f"cuda:{device}"
+    plan = Plan(prob.n, prob.m, prec=prec, device=device)
+    dp = DeviceProblem(prob, dev)
+    do = DeviceOutputs(prob.n, prob.m, prob.T, dev,
+                       dtype=torch.float64 if prec == "fp64" else torch.float32)
+    plan.solve([dp], [do])
+    torch.cuda.synchronize(device)
+    st = int(do.status.item())
+    plan.close()
+    if st != _lib.OK:
+        raise _lib.LQTError(st, "instance status")
+    return do.host()

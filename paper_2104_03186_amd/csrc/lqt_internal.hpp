@@ -1,0 +1,50 @@
+// Internal declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lqt {
+
+enum : uint32_t { kPS_F = 1, kPS_c = 2, kPS_L = 4, kPS_H = 8, kPS_X = 16, kPS_U = 32 };
+
+// Kernel arguments of the lane-per-element pipeline for one instance.
+struct SmallArgs {
+    // problem (device pointers)
+    const double *F, *c, *L, *U, *H, *X, *r, *HT, *XT, *rT, *x0;
+    int64_t T;
+    int32_t n, m, p, pT;
+    uint32_t per_step;
+    // outputs (device pointers; S, v, x, u may be null)
+    double *S, *v, *K, *d, *x, *u;
+    int32_t* status;
+    // workspace
+    double* cst;       // per-instance constants
+    double* der;       // per-step derived data (time-varying problems)
+    double* lane_el;   // [NC] in-wave suffix elements
+    double* wave_val;  // [NG + 1] value function at wavefront-unit starts
+    double* lane_aff;  // [NC] in-wave prefix affine maps
+    double* wave_x;    // [NG] state at wavefront-unit starts
+    int64_t NC;        // number of chunks
+    int32_t B;         // steps per chunk
+    int32_t NG;        // number of wavefront units (64 chunks each)
+    int32_t want_fwd;  // run the forward pass
+};
+
+// Optional per-kernel timing hook: begin/end are called on the host around
+// every kernel launch of a solve (they record HIP events on the stream).
+struct StageHook {
+    void (*begin)(void* ctx, const char* name, hipStream_t s);
+    void (*end)(void* ctx, hipStream_t s);
+    void* ctx;
+};
+
+bool small_supported(int n, int m);
+size_t small_cst_doubles(int n, int m, int p);
+size_t small_der_doubles(int n, int m);
+size_t small_elem_doubles(int n);
+size_t small_aff_doubles(int n);
+size_t small_val_doubles(int n);
+hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook);
+
+}  // namespace lqt
