@@ -23,7 +23,8 @@
  *     Method 1).
  *
  * Memory: every array pointer inside lqt_problem and lqt_outputs is a DEVICE
- * pointer on the plan's device, row-major and contiguous.  The caller owns all
+ * pointer on the plan's device, row-major and contiguous; r and every output
+ * array must be 16-byte aligned (LQT_EINVAL otherwise).  The caller owns all
  * input and output buffers; they must stay valid until the work that reads or
  * writes them has completed (stream-ordered for lqt_solve; until lqt_poll
  * returns something other than LQT_EAGAIN for lqt_submit).  The library owns

@@ -103,9 +103,10 @@ int chunk_length(int64_t T) {
         int b = atoi(e);
         if (b >= 1 && b <= 1024) return b;
     }
-    // Aim at about 128K lanes (two wavefronts per SIMD on 256 CUs).
-    int64_t b = (T + 131071) / 131072;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, b));
+    // About 64K lanes (one wavefront per SIMD on 256 CUs), at most 16 steps
+    // per lane; measured best for the n = 4 pipeline at T = 1e6.
+    int64_t b = (T + 65535) / 65536;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(16, b));
 }
 
 struct Layout {
@@ -155,6 +156,10 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
         return fail(plan, LQT_EINVAL, "instance %d: a required input pointer is NULL", idx);
     if ((p.per_step & LQT_PS_c) && !p.c)
         return fail(plan, LQT_EINVAL, "instance %d: per_step has LQT_PS_c but c is NULL", idx);
+    const void* aligned[] = {p.r, o.S, o.v, o.K, o.d, o.x, o.u};
+    for (const void* q : aligned)
+        if (q && ((uintptr_t)q & 15u))
+            return fail(plan, LQT_EINVAL, "instance %d: r and output arrays must be 16-byte aligned", idx);
     const bool fwd = o.x || o.u;
     if (fwd && (!o.K) != (!o.d))
         return fail(plan, LQT_EINVAL, "instance %d: K and d must both be given or both be NULL", idx);

@@ -31,6 +31,15 @@ namespace lqt {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 
+// Orders this wavefront's LDS accesses around a cooperative transfer.  Each
+// staging area belongs to one wavefront, whose LDS operations execute in
+// order, so only the compiler must be kept from moving accesses across; a
+// workgroup barrier would also drain every outstanding global store.
+LQT_DI void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 LQT_DI void raise_status(int32_t* st, int32_t code) {
     if (st) atomicCAS(st, 0, code);  // first failure wins
 }
@@ -100,18 +109,72 @@ LQT_DI bool step_constants(const double* L, const double* U, const double* H, co
     return ok;
 }
 
-// Time-invariant problems: constants once.  One lane.
+// Same constants when H and X are square (p = n): every input is loaded into
+// registers up front, so the one lane does not wait on a chain of loads.
+template <int N, int M>
+LQT_DI bool step_constants_sq(const double* Lp, const double* Up, const double* Hp, const double* Xp, double* G,
+                              double* J, double* W) {
+    using S = Sym<N>;
+    using SM = Sym<M>;
+    double L[N * M], U[M * M], H[N * N], X[N * N];
+    LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = Lp[i];
+    LQT_UNROLL for (int i = 0; i < M * M; ++i) U[i] = Up[i];
+    LQT_UNROLL for (int i = 0; i < N * N; ++i) H[i] = Hp[i];
+    LQT_UNROLL for (int i = 0; i < N * N; ++i) X[i] = Xp[i];
+    double Us[SM::size], R[M * M], rinv[M];
+    LQT_UNROLL for (int i = 0; i < M; ++i)
+    LQT_UNROLL for (int j = i; j < M; ++j) Us[SM::at(i, j)] = 0.5 * (U[i * M + j] + U[j * M + i]);
+    const bool ok = chol<M>(Us, R, rinv);
+    double Gt[M * N];
+    LQT_UNROLL for (int q = 0; q < M; ++q)
+    LQT_UNROLL for (int i = 0; i < N; ++i) Gt[q * N + i] = L[i * M + q];
+    lsolve<M, N>(R, rinv, Gt);
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int q = 0; q < M; ++q) G[i * M + q] = Gt[q * N + i];
+    double Wl[N * N];
+    mtm<N, N, N>(H, X, Wl);  // H^T X
+    LQT_UNROLL for (int i = 0; i < N * N; ++i) W[i] = Wl[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int j = i; j < N; ++j) {
+        double s = Wl[i * N] * H[j];
+        LQT_UNROLL for (int q = 1; q < N; ++q) s = fma(Wl[i * N + q], H[q * N + j], s);
+        J[S::at(i, j)] = s;
+    }
+    return ok;
+}
+
+// Time-invariant problems: constants once.  One lane; it also initialises the
+// status word (no other kernel of the solve has run yet).
 template <int N, int M>
 __global__ void k_prep_invariant(SmallArgs a) {
     using CL = CstLayout<N, M>;
+    using S = Sym<N>;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double* cst = a.cst;
-    if (!step_constants<N, M>(a.L, a.U, a.H, a.X, a.p, cst + CL::G, cst + CL::J, cst + CL::W))
-        raise_status(a.status, 3);
-    double ST[Sym<N>::size], vT[N];
-    terminal_value<N>(a, ST, vT);
-    LQT_UNROLL for (int i = 0; i < Sym<N>::size; ++i) cst[CL::ST + i] = ST[i];
+    bool ok;
+    double ST[S::size], vT[N];
+    if (a.p == N && a.pT == N) {
+        ok = step_constants_sq<N, M>(a.L, a.U, a.H, a.X, cst + CL::G, cst + CL::J, cst + CL::W);
+        double HT[N * N], XT[N * N], rT[N], Wt[N * N], Xr[N];
+        LQT_UNROLL for (int i = 0; i < N * N; ++i) HT[i] = a.HT[i];
+        LQT_UNROLL for (int i = 0; i < N * N; ++i) XT[i] = a.XT[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) rT[i] = a.rT[i];
+        mtm<N, N, N>(HT, XT, Wt);  // H_T^T X_T
+        mv<N, N>(Wt, rT, Xr);
+        LQT_UNROLL for (int i = 0; i < N; ++i) vT[i] = Xr[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i)
+        LQT_UNROLL for (int j = i; j < N; ++j) {
+            double s = Wt[i * N] * HT[j];
+            LQT_UNROLL for (int q = 1; q < N; ++q) s = fma(Wt[i * N + q], HT[q * N + j], s);
+            ST[S::at(i, j)] = s;
+        }
+    } else {
+        ok = step_constants<N, M>(a.L, a.U, a.H, a.X, a.p, cst + CL::G, cst + CL::J, cst + CL::W);
+        terminal_value<N>(a, ST, vT);
+    }
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) cst[CL::ST + i] = ST[i];
     LQT_UNROLL for (int i = 0; i < N; ++i) cst[CL::VT + i] = vT[i];
+    if (a.status) *a.status = ok ? 0 : 3;
 }
 
 // Time-varying problems: one record (G_k, J_k, eta_k) per step; thread T
@@ -160,10 +223,14 @@ LQT_DI void load_invariant(const SmallArgs& a, Step<N, M>& st) {
     LQT_UNROLL for (int i = 0; i < Sym<N>::size; ++i) st.J[i] = a.cst[CL::J + i];
 }
 
-template <int N, int M, bool VAR>
+// Step data modes: time-invariant with square H, X (the reference row feeds
+// eta directly), time-invariant general, per-step (time-varying).
+enum Mode { kFast = 0, kInv = 1, kVar = 2 };
+
+template <int N, int M, int MODE>
 LQT_DI void load_step(const SmallArgs& a, int64_t k, Step<N, M>& st) {
     using CL = CstLayout<N, M>;
-    if constexpr (VAR) {
+    if constexpr (MODE == kVar) {
         const uint32_t ps = a.per_step;
         const double* F = a.F + ((ps & kPS_F) ? k * N * N : 0);
         LQT_UNROLL for (int i = 0; i < N * N; ++i) st.F[i] = F[i];
@@ -186,24 +253,188 @@ LQT_DI void load_step(const SmallArgs& a, int64_t k, Step<N, M>& st) {
     }
 }
 
+// ---- coalesced transfers -----------------------------------------------------
+//
+// Output rows of one time step k are R contiguous doubles (S_k, K_k, ...).  In
+// the chunked layout lane l of a wavefront handles row (cw0 + l) * B + j at
+// step j, so lanes are B rows apart.  Per-lane stores would issue one small
+// request per lane and per double; instead each lane deposits its row in LDS
+// (row stride R | 1 doubles, conflict-free) and the wavefront writes the 64
+// rows with 16-byte pieces, consecutive lanes on consecutive pieces.
+
+template <int R>
+struct Staged {
+    static constexpr int stride = R | 1;
+    static constexpr int doubles = kWave * stride;
+};
+
+template <int R>
+LQT_DI void lds_put_row(double* lds, int lane, const double* v) {
+    LQT_UNROLL for (int i = 0; i < R; ++i) lds[lane * Staged<R>::stride + i] = v[i];
+}
+
+template <int R>
+LQT_DI void lds_get_row(const double* lds, int lane, double* v) {
+    LQT_UNROLL for (int i = 0; i < R; ++i) v[i] = lds[lane * Staged<R>::stride + i];
+}
+
+// rows (cw0 + rec) * B + j, valid when cw0 + rec < NC and the row < T
+template <int R>
+LQT_DI void wave_store_rows(const double* lds, double* g, int64_t cw0, int64_t NC, int B, int j, int64_t T,
+                            int lane) {
+    constexpr int st = Staged<R>::stride;
+    if constexpr (R % 2 == 0) {
+        constexpr int P = R / 2;
+        LQT_UNROLL for (int it = 0; it < P; ++it) {
+            const int piece = it * kWave + lane;
+            const int rec = piece / P;
+            const int off = (piece - rec * P) * 2;
+            const int64_t c = cw0 + rec;
+            const int64_t row = c * B + j;
+            if (c < NC && row < T) {
+                double2 v;
+                v.x = lds[rec * st + off];
+                v.y = lds[rec * st + off + 1];
+                *reinterpret_cast<double2*>(g + row * R + off) = v;
+            }
+        }
+    } else {
+        LQT_UNROLL for (int it = 0; it < R; ++it) {
+            const int piece = it * kWave + lane;
+            const int rec = piece / R;
+            const int off = piece - rec * R;
+            const int64_t c = cw0 + rec;
+            const int64_t row = c * B + j;
+            if (c < NC && row < T) g[row * R + off] = lds[rec * st + off];
+        }
+    }
+}
+
+template <int R>
+LQT_DI void wave_load_rows(double* lds, const double* g, int64_t cw0, int64_t NC, int B, int j, int64_t T,
+                           int lane) {
+    constexpr int st = Staged<R>::stride;
+    if constexpr (R % 2 == 0) {
+        constexpr int P = R / 2;
+        LQT_UNROLL for (int it = 0; it < P; ++it) {
+            const int piece = it * kWave + lane;
+            const int rec = piece / P;
+            const int off = (piece - rec * P) * 2;
+            const int64_t c = cw0 + rec;
+            const int64_t row = c * B + j;
+            if (c < NC && row < T) {
+                const double2 v = *reinterpret_cast<const double2*>(g + row * R + off);
+                lds[rec * st + off] = v.x;
+                lds[rec * st + off + 1] = v.y;
+            }
+        }
+    } else {
+        LQT_UNROLL for (int it = 0; it < R; ++it) {
+            const int piece = it * kWave + lane;
+            const int rec = piece / R;
+            const int off = piece - rec * R;
+            const int64_t c = cw0 + rec;
+            const int64_t row = c * B + j;
+            if (c < NC && row < T) lds[rec * st + off] = g[row * R + off];
+        }
+    }
+}
+
+// Direct per-lane row store/load with 16-byte pieces when R is even (rows of
+// an even number of doubles keep 16-byte alignment).
+template <int R>
+LQT_DI void store_row(double* g, const double* v) {
+    if constexpr (R % 2 == 0) {
+        LQT_UNROLL for (int i = 0; i < R; i += 2) {
+            double2 t;
+            t.x = v[i];
+            t.y = v[i + 1];
+            *reinterpret_cast<double2*>(g + i) = t;
+        }
+    } else {
+        LQT_UNROLL for (int i = 0; i < R; ++i) g[i] = v[i];
+    }
+}
+
+template <int R>
+LQT_DI void load_row(const double* g, double* v) {
+    if constexpr (R % 2 == 0) {
+        LQT_UNROLL for (int i = 0; i < R; i += 2) {
+            const double2 t = *reinterpret_cast<const double2*>(g + i);
+            v[i] = t.x;
+            v[i + 1] = t.y;
+        }
+    } else {
+        LQT_UNROLL for (int i = 0; i < R; ++i) v[i] = g[i];
+    }
+}
+
+template <int N>
+LQT_DI void full_from_packed(const double* Sv, double* full) {
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int j = 0; j < N; ++j) full[i * N + j] = Sv[Sym<N>::at(i, j)];
+}
+
+// e = W r for W = H^T X square (p = n)
+template <int N>
+LQT_DI void eta_sq(const double* W, const double* rr, double* e) {
+    LQT_UNROLL for (int i = 0; i < N; ++i) {
+        double t = W[i * N] * rr[0];
+        LQT_UNROLL for (int q = 1; q < N; ++q) t = fma(W[i * N + q], rr[q], t);
+        e[i] = t;
+    }
+}
+
 // ---- backward pass ---------------------------------------------------------
 
-template <int N, int M, bool VAR>
+// Row index clamped into the lane's chunk [k0, k1) (any valid row for idle
+// lanes), so prefetch loads are unconditional: loads under branches make the
+// compiler drain every outstanding memory operation at the loop head.
+LQT_DI int64_t clamp_row(int64_t k, int64_t k0, int64_t k1, bool active) {
+    if (!active) return 0;
+    return k < k0 ? k0 : (k >= k1 ? k1 - 1 : k);
+}
+
+template <int N, int M, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bwd_reduce(SmallArgs a) {
+    using CL = CstLayout<N, M>;
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     const bool active = c < a.NC;
     Elem<N> P;
     if (active) {
         Step<N, M> st;
-        if constexpr (!VAR) load_invariant<N, M>(a, st);
+        if constexpr (MODE != kVar) load_invariant<N, M>(a, st);
         const int64_t k0 = c * a.B;
         const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
-        load_step<N, M, VAR>(a, k1 - 1, st);
-        step_elem<N, M>(st, P);
-        for (int64_t k = k1 - 2; k >= k0; --k) {
-            load_step<N, M, VAR>(a, k, st);
-            step_combine<N, M>(st, P);
+        if constexpr (MODE == kFast) {
+            // Rows are consumed k1-1, k1-2, ..., k0.  Two row buffers are
+            // reloaded right after use, two steps ahead of their next use.
+            const double* W = a.cst + CL::W;
+            const double* r = a.r;
+            double rA[N], rB[N];
+            load_row<N>(r + clamp_row(k1 - 1, k0, k1, true) * N, rA);
+            load_row<N>(r + clamp_row(k1 - 2, k0, k1, true) * N, rB);
+            eta_sq<N>(W, rA, st.e);
+            step_elem<N, M>(st, P);
+            load_row<N>(r + clamp_row(k1 - 3, k0, k1, true) * N, rA);
+            for (int64_t k = k1 - 2; k >= k0; k -= 2) {
+                eta_sq<N>(W, rB, st.e);
+                step_combine<N, M>(st, P);
+                load_row<N>(r + clamp_row(k - 2, k0, k1, true) * N, rB);
+                if (k - 1 >= k0) {
+                    eta_sq<N>(W, rA, st.e);
+                    step_combine<N, M>(st, P);
+                }
+                load_row<N>(r + clamp_row(k - 3, k0, k1, true) * N, rA);
+            }
+        } else {
+            load_step<N, M, MODE>(a, k1 - 1, st);
+            step_elem<N, M>(st, P);
+            for (int64_t k = k1 - 2; k >= k0; --k) {
+                load_step<N, M, MODE>(a, k, st);
+                step_combine<N, M>(st, P);
+            }
         }
     } else {
         set_identity<N>(P);
@@ -278,88 +509,146 @@ __global__ __launch_bounds__(kBlock) void k_bwd_top(SmallArgs a, int64_t ld_cst_
     }
 }
 
-template <int N>
-LQT_DI void write_value(const SmallArgs& a, int64_t k, const double* Sv, const double* v, double& fin) {
-    using S = Sym<N>;
-    if (a.S) {
-        double* o = a.S + k * N * N;
-        LQT_UNROLL for (int i = 0; i < N; ++i)
-        LQT_UNROLL for (int j = 0; j < N; ++j) o[i * N + j] = Sv[S::at(i, j)];
-    }
-    if (a.v) {
-        double* o = a.v + k * N;
-        LQT_UNROLL for (int i = 0; i < N; ++i) o[i] = v[i];
-    }
-    LQT_UNROLL for (int i = 0; i < S::size; ++i) fin += Sv[i];
-    LQT_UNROLL for (int i = 0; i < N; ++i) fin += v[i];
+// Per-block copy of the time-invariant step data (read from LDS inside the
+// step loops: after the first output store the compiler could no longer keep
+// such loads on the scalar path).
+template <int N, int M>
+struct InvShared {
+    double F[N * N], L[N * M], U[M * M], J[Sym<N>::size], c[N], W[N * N];
+};
+
+template <int N, int M>
+LQT_DI void load_inv_shared(const SmallArgs& a, InvShared<N, M>& sh) {
+    using CL = CstLayout<N, M>;
+    const int t = threadIdx.x;
+    if (t < N * N) sh.F[t] = a.F[t];
+    if (t < N * M) sh.L[t] = a.L[t];
+    if (t < M * M) sh.U[t] = a.U[t];
+    if (t < Sym<N>::size) sh.J[t] = a.cst[CL::J + t];
+    if (t < N) sh.c[t] = a.c ? a.c[t] : 0.0;
+    if (t < N * N) sh.W[t] = (a.p == N) ? a.cst[CL::W + t] : 0.0;
 }
 
-template <int N, int M, bool VAR>
+template <int N, int M, int MODE, bool ALL>
 __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
     using S = Sym<N>;
     using CL = CstLayout<N, M>;
     constexpr int VS = S::size + N;
+    __shared__ __align__(16) double shS[kBlock / kWave][Staged<N * N>::doubles];
+    __shared__ __align__(16) double shK[kBlock / kWave][Staged<M * N>::doubles];
+    __shared__ InvShared<N, M> inv;
+    if constexpr (MODE != kVar) {
+        load_inv_shared<N, M>(a, inv);
+        __syncthreads();
+    }
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
     const int64_t g = c / kWave;
+    const int64_t cw0 = c - lane;
     const bool active = c < a.NC;
+    const int B = a.B;
+    const int64_t T = a.T;
+    const bool wantS = ALL || a.S, wantV = ALL || a.v;
     Aff<N> phi;
     aff_identity<N>(phi);
+    double Sv[S::size], v[N];
+    const int64_t k0 = c * B;
+    const int64_t k1 = (k0 + B < T) ? k0 + B : T;
+    double fin = 0.0;
+    bool ok = true;
     if (active) {
-        double Sv[S::size], v[N];
-        const double* wv = a.wave_val + (g + 1 < a.NG ? g + 1 : a.NG) * VS;
-        LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = wv[i];
-        LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = wv[S::size + i];
+        const double* wvp = a.wave_val + (g + 1) * VS;
+        LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = wvp[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = wvp[S::size + i];
         if (lane < kWave - 1 && c + 1 < a.NC) {
             Elem<N> nx;
             load_elem<N>(a.lane_el + (c + 1) * Elem<N>::size, nx);
             anchor<N>(nx, Sv, v);
         }
-        const int64_t k0 = c * a.B;
-        const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
-        double fin = 0.0;
-        if (k1 == a.T) write_value<N>(a, a.T, Sv, v, fin);
-        // invariant step data
-        double F[N * N], cc[N], L[N * M], U[M * M], Js[S::size], e[N];
-        const uint32_t ps = a.per_step;
-        bool ok = true;
-        for (int64_t k = k1 - 1; k >= k0; --k) {
-            const double* Fp = a.F + ((VAR && (ps & kPS_F)) ? k * N * N : 0);
-            const double* Lp = a.L + ((VAR && (ps & kPS_L)) ? k * N * M : 0);
-            const double* Up = a.U + ((VAR && (ps & kPS_U)) ? k * M * M : 0);
-            const double* cp = a.c ? a.c + ((VAR && (ps & kPS_c)) ? k * N : 0) : nullptr;
-            LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = Fp[i];
-            LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = Lp[i];
-            LQT_UNROLL for (int i = 0; i < M * M; ++i) U[i] = Up[i];
-            LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = cp ? cp[i] : 0.0;
-            if constexpr (VAR) {
+        if (k1 == T) {  // terminal value S_T, v_T
+            double full[N * N];
+            full_from_packed<N>(Sv, full);
+            if (wantS) store_row<N * N>(a.S + T * N * N, full);
+            if (wantV) store_row<N>(a.v + T * N, v);
+        }
+    }
+    const uint32_t ps = a.per_step;
+    const int p = a.p;
+    auto body = [&](int j, const double* rr) {
+        const int64_t k = k0 + j;
+        if (active && k < k1) {
+            double F[N * N], cc[N], L[N * M], U[M * M], Js[S::size], e[N];
+            if constexpr (MODE == kVar) {
+                const double* Fp = a.F + ((ps & kPS_F) ? k * N * N : 0);
+                const double* Lp = a.L + ((ps & kPS_L) ? k * N * M : 0);
+                const double* Up = a.U + ((ps & kPS_U) ? k * M * M : 0);
+                const double* cp = a.c ? a.c + ((ps & kPS_c) ? k * N : 0) : nullptr;
+                LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = Fp[i];
+                LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = Lp[i];
+                LQT_UNROLL for (int i = 0; i < M * M; ++i) U[i] = Up[i];
+                LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = cp ? cp[i] : 0.0;
                 const double* rec = a.der + k * CL::der;
                 LQT_UNROLL for (int i = 0; i < S::size; ++i) Js[i] = rec[N * M + i];
                 LQT_UNROLL for (int i = 0; i < N; ++i) e[i] = rec[N * M + S::size + i];
             } else {
-                LQT_UNROLL for (int i = 0; i < S::size; ++i) Js[i] = a.cst[CL::J + i];
-                const int p = a.p;
-                const double* W = a.cst + CL::W;
-                const double* r = a.r + k * p;
-                LQT_UNROLL for (int i = 0; i < N; ++i) e[i] = 0.0;
-                for (int q = 0; q < p; ++q) {
-                    const double rq = r[q];
-                    LQT_UNROLL for (int i = 0; i < N; ++i) e[i] = fma(W[i * p + q], rq, e[i]);
+                LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = inv.F[i];
+                LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = inv.L[i];
+                LQT_UNROLL for (int i = 0; i < M * M; ++i) U[i] = inv.U[i];
+                LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = inv.c[i];
+                LQT_UNROLL for (int i = 0; i < S::size; ++i) Js[i] = inv.J[i];
+                if constexpr (MODE == kFast) {
+                    eta_sq<N>(inv.W, rr, e);
+                } else {
+                    const double* W = a.cst + CL::W;
+                    const double* r = a.r + k * p;
+                    LQT_UNROLL for (int i = 0; i < N; ++i) e[i] = 0.0;
+                    for (int q = 0; q < p; ++q) {
+                        const double rq = r[q];
+                        LQT_UNROLL for (int i = 0; i < N; ++i) e[i] = fma(W[i * p + q], rq, e[i]);
+                    }
                 }
             }
             double K[M * N], d[M], Ft[N * N], ct[N];
             ok = riccati_step<N, M>(F, cc, L, U, Js, e, Sv, v, K, d, Ft, ct) && ok;
-            write_value<N>(a, k, Sv, v, fin);
-            double* Ko = a.K + k * M * N;
-            LQT_UNROLL for (int i = 0; i < M * N; ++i) Ko[i] = K[i];
-            double* dO = a.d + k * M;
-            LQT_UNROLL for (int i = 0; i < M; ++i) dO[i] = d[i];
+            LQT_UNROLL for (int i = 0; i < S::size; ++i) fin += Sv[i];
+            LQT_UNROLL for (int i = 0; i < N; ++i) fin += v[i];
+            if (wantS) {
+                double full[N * N];
+                full_from_packed<N>(Sv, full);
+                lds_put_row<N * N>(shS[wv], lane, full);
+            }
+            lds_put_row<M * N>(shK[wv], lane, K);
+            if (wantV) store_row<N>(a.v + k * N, v);
+            store_row<M>(a.d + k * M, d);
             // compose the chunk map: phi <- phi o (Ft, ct)
             Aff<N> step;
             LQT_UNROLL for (int i = 0; i < N * N; ++i) step.F[i] = Ft[i];
             LQT_UNROLL for (int i = 0; i < N; ++i) step.c[i] = ct[i];
             aff_after<N>(step, phi);
         }
+        wave_sync();
+        if (wantS) wave_store_rows<N * N>(shS[wv], a.S, cw0, a.NC, B, j, T, lane);
+        wave_store_rows<M * N>(shK[wv], a.K, cw0, a.NC, B, j, T, lane);
+        wave_sync();
+    };
+    // Reference rows (fast mode): step j uses rA when B-1-j is even, rB
+    // otherwise; each buffer is reloaded right after use.
+    double rA[N], rB[N];
+    auto fetch = [&](int j, double* buf) {
+        if constexpr (MODE == kFast) load_row<N>(a.r + clamp_row(k0 + j, k0, k1, active) * N, buf);
+    };
+    fetch(B - 1, rA);
+    fetch(B - 2, rB);
+    for (int j = B - 1; j >= 0; j -= 2) {
+        body(j, rA);
+        fetch(j - 2, rA);
+        if (j - 1 >= 0) {
+            body(j - 1, rB);
+            fetch(j - 3, rB);
+        }
+    }
+    if (active) {
         if (!ok) raise_status(a.status, 3);
         if (!isfinite(fin)) raise_status(a.status, 4);
     }
@@ -370,6 +659,64 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
         if (lane >= d) aff_after<N>(Q, phi);
     }
     if (active) store_aff<N>(a.lane_aff + c * Aff<N>::size, phi);
+}
+
+// Forward roll-out with a compile-time chunk length: every gain row of the
+// chunk is loaded into registers before the first store.
+template <int N, int M, int BC>
+__global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.NC) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t T = a.T;
+    const int64_t k0 = c * BC;
+    const int64_t k1 = (k0 + BC < T) ? k0 + BC : T;
+    constexpr int KD = M * N + M;
+    double gk[BC][KD];
+    LQT_UNROLL for (int j = 0; j < BC; ++j) {
+        const int64_t kk = clamp_row(k0 + j, k0, k1, true);
+        load_row<M * N>(a.K + kk * M * N, gk[j]);
+        load_row<M>(a.d + kk * M, gk[j] + M * N);
+    }
+    double F[N * N], L[N * M], cc[N];
+    LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = a.F[i];
+    LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = a.L[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = a.c ? a.c[i] : 0.0;
+    double x[N], t[N];
+    const int64_t g = c / kWave;
+    LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = a.wave_x[g * N + i];
+    if (lane > 0) {
+        Aff<N> pre;
+        load_aff<N>(a.lane_aff + (c - 1) * Aff<N>::size, pre);
+        mv<N, N>(pre.F, x, t);
+        LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = t[i] + pre.c[i];
+    }
+    double fin = 0.0;
+    LQT_UNROLL for (int j = 0; j < BC; ++j) {
+        const int64_t k = k0 + j;
+        double u[M];
+        LQT_UNROLL for (int q = 0; q < M; ++q) {
+            double s = gk[j][M * N + q];
+            LQT_UNROLL for (int i = 0; i < N; ++i) s = fma(-gk[j][q * N + i], x[i], s);
+            u[q] = s;
+        }
+        LQT_UNROLL for (int i = 0; i < N; ++i) {
+            double s = cc[i];
+            LQT_UNROLL for (int q = 0; q < N; ++q) s = fma(F[i * N + q], x[q], s);
+            LQT_UNROLL for (int q = 0; q < M; ++q) s = fma(L[i * M + q], u[q], s);
+            t[i] = s;
+        }
+        if (k < k1) {
+            store_row<N>(a.x + k * N, x);
+            store_row<M>(a.u + k * M, u);
+            LQT_UNROLL for (int i = 0; i < N; ++i) {
+                x[i] = t[i];
+                fin += t[i];
+            }
+        }
+    }
+    if (k1 == T) store_row<N>(a.x + T * N, x);
+    if (!isfinite(fin)) raise_status(a.status, 4);
 }
 
 // ---- forward pass ----------------------------------------------------------
@@ -425,13 +772,35 @@ __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
     }
 }
 
-template <int N, int M, bool VAR>
+template <int N, int M, int MODE, bool ALL>
 __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.NC) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t g = c / kWave;
+    const int B = a.B;
+    const int64_t T = a.T;
+    const int64_t k0 = c * B;
+    const int64_t k1 = (k0 + B < T) ? k0 + B : T;
+    const bool wantX = ALL || a.x, wantU = ALL || a.u;
+    constexpr int KD = M * N + M;  // one gain row: K_k then d_k
+    auto load_gain = [&](int64_t k, double* gk) {
+        const int64_t kk = clamp_row(k, k0, k1, true);
+        load_row<M * N>(a.K + kk * M * N, gk);
+        load_row<M>(a.d + kk * M, gk + M * N);
+    };
+    const uint32_t ps = a.per_step;
+    // time-invariant F, L, c stay in registers for the whole chunk
+    double F0[N * N], L0[N * M], c0[N];
+    if constexpr (MODE != kVar) {
+        LQT_UNROLL for (int i = 0; i < N * N; ++i) F0[i] = a.F[i];
+        LQT_UNROLL for (int i = 0; i < N * M; ++i) L0[i] = a.L[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) c0[i] = a.c ? a.c[i] : 0.0;
+    }
+    double gA[KD], gB[KD];
+    load_gain(k0, gA);
+    load_gain(k0 + 1, gB);
     double x[N], t[N];
+    const int64_t g = c / kWave;
     LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = a.wave_x[g * N + i];
     if (lane > 0) {
         Aff<N> pre;
@@ -439,42 +808,47 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
         mv<N, N>(pre.F, x, t);
         LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = t[i] + pre.c[i];
     }
-    const int64_t k0 = c * a.B;
-    const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
-    const uint32_t ps = a.per_step;
     double fin = 0.0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const double* Fp = a.F + ((VAR && (ps & kPS_F)) ? k * N * N : 0);
-        const double* Lp = a.L + ((VAR && (ps & kPS_L)) ? k * N * M : 0);
-        const double* cp = a.c ? a.c + ((VAR && (ps & kPS_c)) ? k * N : 0) : nullptr;
-        const double* Kp = a.K + k * M * N;
-        const double* dp = a.d + k * M;
+    auto step = [&](int64_t k, const double* gk) {
+        double F[N * N], L[N * M], cc[N];
+        if constexpr (MODE == kVar) {
+            const double* Fp = a.F + ((ps & kPS_F) ? k * N * N : 0);
+            const double* Lp = a.L + ((ps & kPS_L) ? k * N * M : 0);
+            const double* cp = a.c ? a.c + ((ps & kPS_c) ? k * N : 0) : nullptr;
+            LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = Fp[i];
+            LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = Lp[i];
+            LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = cp ? cp[i] : 0.0;
+        } else {
+            LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = F0[i];
+            LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = L0[i];
+            LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = c0[i];
+        }
         double u[M];
-        LQT_UNROLL for (int p = 0; p < M; ++p) {
-            double s = dp[p];
-            LQT_UNROLL for (int j = 0; j < N; ++j) s = fma(-Kp[p * N + j], x[j], s);
-            u[p] = s;
+        LQT_UNROLL for (int q = 0; q < M; ++q) {
+            double s = gk[M * N + q];
+            LQT_UNROLL for (int i = 0; i < N; ++i) s = fma(-gk[q * N + i], x[i], s);
+            u[q] = s;
         }
-        if (a.x) {
-            LQT_UNROLL for (int i = 0; i < N; ++i) a.x[k * N + i] = x[i];
-        }
-        if (a.u) {
-            LQT_UNROLL for (int p = 0; p < M; ++p) a.u[k * M + p] = u[p];
-        }
+        if (wantX) store_row<N>(a.x + k * N, x);
+        if (wantU) store_row<M>(a.u + k * M, u);
         LQT_UNROLL for (int i = 0; i < N; ++i) {
-            double s = cp ? cp[i] : 0.0;
-            LQT_UNROLL for (int j = 0; j < N; ++j) s = fma(Fp[i * N + j], x[j], s);
-            LQT_UNROLL for (int p = 0; p < M; ++p) s = fma(Lp[i * M + p], u[p], s);
+            double s = cc[i];
+            LQT_UNROLL for (int q = 0; q < N; ++q) s = fma(F[i * N + q], x[q], s);
+            LQT_UNROLL for (int q = 0; q < M; ++q) s = fma(L[i * M + q], u[q], s);
             t[i] = s;
         }
         LQT_UNROLL for (int i = 0; i < N; ++i) {
             x[i] = t[i];
             fin += t[i];
         }
+    };
+    for (int64_t k = k0; k < k1; k += 2) {
+        step(k, gA);
+        load_gain(k + 2, gA);
+        if (k + 1 < k1) step(k + 1, gB);
+        load_gain(k + 3, gB);
     }
-    if (k1 == a.T && a.x) {
-        LQT_UNROLL for (int i = 0; i < N; ++i) a.x[a.T * N + i] = x[i];
-    }
+    if (k1 == T && wantX) store_row<N>(a.x + T * N, x);
     if (!isfinite(fin)) raise_status(a.status, 4);
 }
 
@@ -491,30 +865,27 @@ struct Stage {
     }
 };
 
-template <int N, int M>
-static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* h) {
+template <int N, int M, int MODE>
+static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     using CL = CstLayout<N, M>;
-    const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
     const unsigned grid = (unsigned)((a.NC + kBlock - 1) / kBlock);
-    {
-        Stage st(h, "init_status", s);
-        k_init_status<<<1, 64, 0, s>>>(a.status);
-    }
-    if (var) {
+    const bool all = a.S && a.v && a.x && a.u;
+    const bool even = (N % 2 == 0) && (M % 2 == 0);
+    if (MODE == kVar) {
+        {
+            Stage st(h, "init_status", s);
+            k_init_status<<<1, 64, 0, s>>>(a.status);
+        }
         const unsigned pg = (unsigned)((a.T + 1 + kBlock - 1) / kBlock);
-        {
-            Stage st(h, "prep_varying", s);
-            k_prep_varying<N, M><<<pg, kBlock, 0, s>>>(a);
-        }
-        Stage st(h, "bwd_reduce", s);
-        k_bwd_reduce<N, M, true><<<grid, kBlock, 0, s>>>(a);
+        Stage st(h, "prep_varying", s);
+        k_prep_varying<N, M><<<pg, kBlock, 0, s>>>(a);
     } else {
-        {
-            Stage st(h, "prep_invariant", s);
-            k_prep_invariant<N, M><<<1, 64, 0, s>>>(a);
-        }
+        Stage st(h, "prep_invariant", s);
+        k_prep_invariant<N, M><<<1, 64, 0, s>>>(a);
+    }
+    {
         Stage st(h, "bwd_reduce", s);
-        k_bwd_reduce<N, M, false><<<grid, kBlock, 0, s>>>(a);
+        k_bwd_reduce<N, M, MODE><<<grid, kBlock, 0, s>>>(a);
     }
     {
         Stage st(h, "bwd_top", s);
@@ -522,8 +893,8 @@ static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* 
     }
     {
         Stage st(h, "bwd_final", s);
-        if (var) k_bwd_final<N, M, true><<<grid, kBlock, 0, s>>>(a);
-        else k_bwd_final<N, M, false><<<grid, kBlock, 0, s>>>(a);
+        if (all) k_bwd_final<N, M, MODE, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bwd_final<N, M, MODE, false><<<grid, kBlock, 0, s>>>(a);
     }
     if (a.want_fwd) {
         {
@@ -531,9 +902,27 @@ static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* 
             k_fwd_top<N><<<1, kBlock, 0, s>>>(a);
         }
         Stage st(h, "fwd_final", s);
-        if (var) k_fwd_final<N, M, true><<<grid, kBlock, 0, s>>>(a);
-        else k_fwd_final<N, M, false><<<grid, kBlock, 0, s>>>(a);
+        const bool regs = MODE != kVar && all && even;
+        bool fdone = false;
+        if constexpr (N % 2 == 0 && M % 2 == 0) {
+            fdone = true;
+            if (regs && a.B == 4) k_fwd_final_regs<N, M, 4><<<grid, kBlock, 0, s>>>(a);
+            else if (regs && a.B == 8) k_fwd_final_regs<N, M, 8><<<grid, kBlock, 0, s>>>(a);
+            else if (regs && a.B == 16) k_fwd_final_regs<N, M, 16><<<grid, kBlock, 0, s>>>(a);
+            else fdone = false;
+        }
+        if (fdone) {
+        } else if (all) k_fwd_final<N, M, MODE, true><<<grid, kBlock, 0, s>>>(a);
+        else k_fwd_final<N, M, MODE, false><<<grid, kBlock, 0, s>>>(a);
     }
+}
+
+template <int N, int M>
+static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* h) {
+    const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
+    if (var) run_mode<N, M, kVar>(a, s, h);
+    else if (a.p == N) run_mode<N, M, kFast>(a, s, h);
+    else run_mode<N, M, kInv>(a, s, h);
     return hipGetLastError();
 }
 

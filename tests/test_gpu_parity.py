@@ -83,7 +83,7 @@ def test_tracking_default_chunk(api, plan, T):
     assert_parity(do.host(), oracle.solve(prob))
 
 
-@pytest.mark.parametrize("chunk", [1, 3, 8, 33])
+@pytest.mark.parametrize("chunk", [1, 3, 4, 8, 16, 33])
 @pytest.mark.parametrize("T", [1, 7, 64, 65, 1000, 4097, 20000])
 def test_tracking_chunk_sizes(api, plan, T, chunk):
     _say("tracking n=4 m=2 T=", T, "chunk=", chunk)
