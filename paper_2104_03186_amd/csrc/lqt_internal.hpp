@@ -39,6 +39,25 @@ struct StageHook {
     void* ctx;
 };
 
+// One instance of the wavefront-per-chunk pipeline (device-resident array).
+struct GInst {
+    const double *F, *c, *L, *U, *H, *X, *r, *HT, *XT, *rT, *x0;
+    double *S, *v, *K, *d, *x, *u;
+    int32_t* status;
+    int64_t T;
+    int32_t n, m, p, pT;
+    uint32_t per_step;
+    int32_t B;        // steps per chunk
+    int64_t NC;       // chunks
+    int64_t chunk0;   // flat index of the first chunk over the launch
+    double* ws;       // instance workspace (wave_inst_ws_doubles)
+};
+
+int64_t wave_inst_ws_doubles(int n, int m, int p, int64_t NC);
+size_t wave_lds_bytes(int nmax);
+hipError_t wave_solve(const GInst* d_inst, int ninst, int64_t nchunks, int nmax, bool want_fwd, hipStream_t s,
+                      const StageHook* h);
+
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);
 size_t small_der_doubles(int n, int m);

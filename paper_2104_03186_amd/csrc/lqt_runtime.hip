@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -19,7 +20,32 @@
 
 namespace {
 
-constexpr int kMaxNx = 4;  // largest state dimension of this build's kernels
+constexpr int kMaxNx = 32;         // largest state dimension of this build's kernels
+constexpr int kWaveMaxN = 32;      // wavefront path: n, m, p, pT up to this
+constexpr int64_t kSmallMinT = 8192;  // lane-per-element path for long n <= 4 instances
+
+// Path of an instance: a function of the instance alone (never of the batch),
+// so a result is the same alone and in any mix.  LQT_PATH=small|wave forces
+// one path where it applies (tests).
+enum class Path { Small, Wave };
+
+Path path_of(const lqt_problem& p) {
+    int force = 0;
+    if (const char* e = getenv("LQT_PATH")) force = !strcmp(e, "small") ? 1 : (!strcmp(e, "wave") ? 2 : 0);
+    const bool small_ok = lqt::small_supported(p.nx, p.nu);
+    if (force == 1 && small_ok) return Path::Small;
+    if (force == 2) return Path::Wave;
+    return (small_ok && p.T >= kSmallMinT) ? Path::Small : Path::Wave;
+}
+
+int wave_chunk(int64_t T) {
+    if (const char* e = getenv("LQT_WCHUNK")) {
+        int b = atoi(e);
+        if (b >= 1 && b <= 4096) return b;
+    }
+    int64_t b = (T + 63) / 64;
+    return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
+}
 
 thread_local std::string g_create_error;
 
@@ -79,6 +105,11 @@ struct lqt_plan_s {
     uint64_t next_ticket = 1;
     std::unordered_map<uint64_t, Request> inflight;
     std::vector<int32_t*> free_status;
+    // wavefront path: pinned host copy of the instance table and the event of
+    // its last upload (the buffer is reused only after that copy finished)
+    lqt::GInst* ginst_host = nullptr;
+    size_t ginst_cap = 0;
+    hipEvent_t ginst_done = nullptr;
 };
 
 namespace {
@@ -149,8 +180,9 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
-    if (!lqt::small_supported(p.nx, p.nu))
-        return fail(plan, LQT_ENOTSUP, "instance %d: nx=%d nu=%d not provided by this build", idx, p.nx, p.nu);
+    if (path_of(p) == Path::Wave && std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
+        return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
+                    p.nu, p.ny, p.nyT, kWaveMaxN);
     if (p.per_step & ~63u) return fail(plan, LQT_EINVAL, "instance %d: unknown per_step bits 0x%x", idx, p.per_step);
     if (!p.F || !p.L || !p.H || !p.X || !p.U || !p.r || !p.HT || !p.XT || !p.rT || !p.x0)
         return fail(plan, LQT_EINVAL, "instance %d: a required input pointer is NULL", idx);
@@ -255,6 +287,14 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
                     probe.nx = n; probe.nu = m; probe.ny = n;
                     need = std::max(need, layout_for(probe, true, true).total);
                 }
+        // and for one wavefront-path instance of the largest dimensions
+        {
+            const int64_t B = wave_chunk(desc->max_steps);
+            const int64_t NC = (desc->max_steps + B - 1) / B;
+            const size_t w = (size_t)lqt::wave_inst_ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, NC) * 8 +
+                             (size_t)desc->max_steps * (desc->max_nu * desc->max_nx + desc->max_nu) * 8 + 4096;
+            need = std::max(need, w);
+        }
         lqt_status st = ensure_ws(p, need);
         if (st != LQT_OK) {
             g_create_error = p->err;
@@ -266,6 +306,102 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     return LQT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Solve a set of instances on stream s.  status_override (if not null) gives
+// a per-instance device status word used instead of outs[i].status.
+lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
+                     hipStream_t s, int32_t* const* status_override) {
+    // partition by path
+    std::vector<int> small, wave;
+    for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
+    // workspace: [small-path region (largest small instance)] [wave region]
+    size_t small_need = 0;
+    for (int i : small) small_need = std::max(small_need, layout_for(probs[i], !outs[i].K, !outs[i].d).total);
+    small_need = align_up(small_need);
+    size_t wave_need = 0;
+    int nmax = 1;
+    int64_t nchunks = 0;
+    std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
+    for (size_t j = 0; j < wave.size(); ++j) {
+        const lqt_problem& p = probs[wave[j]];
+        const int B = wave_chunk(p.T);
+        const int64_t NC = (p.T + B - 1) / B;
+        nchunks += NC;
+        nmax = std::max(nmax, std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
+        ws_off[j] = (int64_t)wave_need;
+        wave_need = align_up(wave_need + (size_t)lqt::wave_inst_ws_doubles(p.nx, p.nu, p.ny, NC) * sizeof(double));
+        kd_off[j] = (int64_t)wave_need;
+        const lqt_outputs& o = outs[wave[j]];
+        if (!o.K || !o.d)
+            wave_need = align_up(wave_need + (size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double));
+    }
+    const size_t inst_bytes = align_up(wave.size() * sizeof(lqt::GInst));
+    const size_t total = small_need + (wave.empty() ? 0 : wave_need + inst_bytes);
+    lqt_status st = ensure_ws(plan, total);
+    if (st != LQT_OK) return st;
+    for (int i : small) {
+        st = launch_one(plan, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
+        if (st != LQT_OK) return st;
+    }
+    if (wave.empty()) return LQT_OK;
+    if (plan->ginst_cap < wave.size()) {
+        if (plan->ginst_done) (void)hipEventSynchronize(plan->ginst_done);
+        if (plan->ginst_host) (void)hipHostFree(plan->ginst_host);
+        plan->ginst_host = nullptr;
+        plan->ginst_cap = 0;
+        if (hipHostMalloc((void**)&plan->ginst_host, wave.size() * sizeof(lqt::GInst), 0) != hipSuccess)
+            return fail(plan, LQT_ENOMEM, "pinned instance table allocation failed");
+        plan->ginst_cap = wave.size();
+    } else if (plan->ginst_done) {
+        (void)hipEventSynchronize(plan->ginst_done);  // previous upload has left the buffer
+    }
+    char* wbase = plan->ws + small_need;
+    bool want_fwd = false;
+    int64_t chunk0 = 0;
+    for (size_t j = 0; j < wave.size(); ++j) {
+        const lqt_problem& p = probs[wave[j]];
+        const lqt_outputs& o = outs[wave[j]];
+        lqt::GInst& g = plan->ginst_host[j];
+        g = lqt::GInst{};
+        g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
+        g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
+        g.S = (double*)o.S; g.v = (double*)o.v; g.x = (double*)o.x; g.u = (double*)o.u;
+        double* kd = (double*)(wbase + kd_off[j]);
+        g.K = o.K ? (double*)o.K : kd;
+        g.d = o.d ? (double*)o.d : kd + (size_t)p.T * p.nu * p.nx;
+        g.status = status_override ? status_override[wave[j]] : o.status;
+        g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
+        g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+        g.B = wave_chunk(p.T);
+        g.NC = (p.T + g.B - 1) / g.B;
+        g.chunk0 = chunk0;
+        chunk0 += g.NC;
+        g.ws = (double*)(wbase + ws_off[j]);
+        // forward pass only if some instance of the launch wants it; instances
+        // without x and u still get their (cheap) roll-out into K/d-free paths
+        if (o.x || o.u) want_fwd = true;
+    }
+    lqt::GInst* d_inst = (lqt::GInst*)(wbase + wave_need);
+    if (hipMemcpyAsync(d_inst, plan->ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return fail(plan, LQT_EHIP, "instance table upload failed");
+    if (!plan->ginst_done && hipEventCreateWithFlags(&plan->ginst_done, hipEventDisableTiming) != hipSuccess)
+        return fail(plan, LQT_EHIP, "event creation failed");
+    (void)hipEventRecord(plan->ginst_done, s);
+    lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
+    hipError_t e = lqt::wave_solve(d_inst, (int)wave.size(), nchunks, nmax, want_fwd, s,
+                                   plan->prof.on ? &hook : nullptr);
+    if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
+    return LQT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
                      void* stream) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_solve: NULL plan");
@@ -275,20 +411,9 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
         lqt_status st = validate(plan, probs[i], outs[i], i);
         if (st != LQT_OK) return st;
     }
+    if (count == 0) return LQT_OK;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-    // Workspace for the largest instance first, so no reallocation happens
-    // between launches of this call.
-    size_t need = 0;
-    for (int i = 0; i < count; ++i)
-        need = std::max(need, layout_for(probs[i], !outs[i].K, !outs[i].d).total);
-    lqt_status st = ensure_ws(plan, need);
-    if (st != LQT_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    for (int i = 0; i < count; ++i) {
-        st = launch_one(plan, probs[i], outs[i], s, nullptr);
-        if (st != LQT_OK) return st;
-    }
-    return LQT_OK;
+    return solve_all(plan, probs, outs, count, (hipStream_t)stream, nullptr);
 }
 
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, uint64_t* ticket) {
@@ -314,8 +439,8 @@ lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_output
     } else if (hipMalloc(&r.status_dev, sizeof(int32_t)) != hipSuccess) {
         return fail(plan, LQT_ENOMEM, "lqt_submit: status allocation failed");
     }
-    st = ensure_ws(plan, L.total);
-    if (st == LQT_OK) st = launch_one(plan, *prob, *out, plan->serve_stream, r.status_dev);
+    int32_t* ovr[1] = {r.status_dev};
+    st = solve_all(plan, prob, out, 1, plan->serve_stream, ovr);
     if (st == LQT_OK && out->status)
         if (hipMemcpyAsync(out->status, r.status_dev, sizeof(int32_t), hipMemcpyDeviceToDevice,
                            plan->serve_stream) != hipSuccess)
@@ -369,6 +494,8 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
+    if (plan->ginst_done) (void)hipEventDestroy(plan->ginst_done);
+    if (plan->ginst_host) (void)hipHostFree(plan->ginst_host);
     if (plan->ws) (void)hipFree(plan->ws);
     delete plan;
     return LQT_OK;

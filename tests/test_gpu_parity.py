@@ -42,12 +42,15 @@ def plan(api):
 
 
 @pytest.fixture(autouse=True)
-def _no_chunk_env():
-    old = os.environ.pop("LQT_CHUNK", None)
+def _small_path_env():
+    """These tests exercise the lane-per-element path (n <= 4) at every T."""
+    saved = {k: os.environ.pop(k, None) for k in ("LQT_CHUNK", "LQT_PATH")}
+    os.environ["LQT_PATH"] = "small"
     yield
-    os.environ.pop("LQT_CHUNK", None)
-    if old is not None:
-        os.environ["LQT_CHUNK"] = old
+    for k, v in saved.items():
+        os.environ.pop(k, None)
+        if v is not None:
+            os.environ[k] = v
 
 
 def solve(api, plan, prob, want=FAMILIES, chunk=None):
