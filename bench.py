@@ -57,6 +57,58 @@ def path_flops_per_step(n, m):
     return 2 * comb + extract + 2 * aff
 
 
+def run_batched(args, api, inputs, torch):
+    """Uneven batch: 4096 instances, T log-uniform on [256, 16384], n in
+    {4, 8, 16}, m = n / 2, diagonal costs, random-walk references; one
+    lqt_solve call per step (all instances, every output family)."""
+    count = args.count
+    shapes = inputs.batched_shapes(count)
+    probs = [inputs.diag_problem(n, n // 2, T, 2, i) for i, (n, T) in enumerate(shapes)]
+    steps_total = sum(p.T for p in probs)
+    plan = api.Plan(16, 8, prec="fp64", device=0)
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [api.DeviceOutputs(p.n, p.m, p.T) for p in probs]
+    stream = torch.cuda.current_stream(0)
+    for _ in range(args.warmup):
+        plan.solve(dps, dos, stream)
+    torch.cuda.synchronize()
+    status_bad = sum(int(o.status.item()) != 0 for o in dos)
+    rel_err = None
+    if not args.no_parity:
+        import oracle
+
+        worst = {f: 0.0 for f in api.FAMILIES}
+        for i in range(0, count, max(1, count // 16)):
+            ref = oracle.solve(probs[i])
+            got = dos[i].host()
+            for f in api.FAMILIES:
+                worst[f] = max(worst[f], float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])))
+        rel_err = worst
+    plan.profile(True)
+    plan.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.solve(dps, dos, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stages = plan.profile_read()
+    plan.profile(False)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.solve(dps, dos, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, FP64", "steps_per_solve": steps_total,
+           "ms_per_solve": round(ms, 3), "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s",
+           "status_failures": status_bad, "rel_err_sampled": rel_err,
+           "stages_ms_per_solve": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages.items()}}
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--workload", choices=("single", "batched"), default="single")
+    ap.add_argument("--count", type=int, default=4096)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -76,6 +130,10 @@ def main():
     import torch
 
     from paper_2104_03186_amd import api, inputs
+
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, api, inputs, torch)), flush=True)
+        return
 
     n, m, T = 4, 2, args.T
     prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)

@@ -55,7 +55,12 @@ struct GInst {
 
 int64_t wave_inst_ws_doubles(int n, int m, int p, int64_t NC);
 size_t wave_lds_bytes(int nmax);
-hipError_t wave_solve(const GInst* d_inst, int ninst, int64_t nchunks, int nmax, bool want_fwd, hipStream_t s,
+
+// Size-class variant of the wavefront pipeline: matrices zero-padded to N x N
+// with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
+int tile_class(int need);
+size_t tile_lds_bytes(int N);
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
                       const StageHook* h);
 
 bool small_supported(int n, int m);

@@ -314,23 +314,24 @@ namespace {
 // a per-instance device status word used instead of outs[i].status.
 lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
                      hipStream_t s, int32_t* const* status_override) {
-    // partition by path
+    // partition by path; wavefront instances ordered by size class
     std::vector<int> small, wave;
     for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
+    auto cls = [&](int i) {
+        const lqt_problem& p = probs[i];
+        return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
+    };
+    std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
     // workspace: [small-path region (largest small instance)] [wave region]
     size_t small_need = 0;
     for (int i : small) small_need = std::max(small_need, layout_for(probs[i], !outs[i].K, !outs[i].d).total);
     small_need = align_up(small_need);
     size_t wave_need = 0;
-    int nmax = 1;
-    int64_t nchunks = 0;
     std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
     for (size_t j = 0; j < wave.size(); ++j) {
         const lqt_problem& p = probs[wave[j]];
         const int B = wave_chunk(p.T);
         const int64_t NC = (p.T + B - 1) / B;
-        nchunks += NC;
-        nmax = std::max(nmax, std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
         ws_off[j] = (int64_t)wave_need;
         wave_need = align_up(wave_need + (size_t)lqt::wave_inst_ws_doubles(p.nx, p.nu, p.ny, NC) * sizeof(double));
         kd_off[j] = (int64_t)wave_need;
@@ -359,9 +360,10 @@ lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
         (void)hipEventSynchronize(plan->ginst_done);  // previous upload has left the buffer
     }
     char* wbase = plan->ws + small_need;
-    bool want_fwd = false;
+    std::vector<char> want_fwd_c(wave.size(), 0);
     int64_t chunk0 = 0;
     for (size_t j = 0; j < wave.size(); ++j) {
+        if (j > 0 && cls(wave[j]) != cls(wave[j - 1])) chunk0 = 0;  // each class numbers its own chunks
         const lqt_problem& p = probs[wave[j]];
         const lqt_outputs& o = outs[wave[j]];
         lqt::GInst& g = plan->ginst_host[j];
@@ -382,7 +384,7 @@ lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
         g.ws = (double*)(wbase + ws_off[j]);
         // forward pass only if some instance of the launch wants it; instances
         // without x and u still get their (cheap) roll-out into K/d-free paths
-        if (o.x || o.u) want_fwd = true;
+        want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
     }
     lqt::GInst* d_inst = (lqt::GInst*)(wbase + wave_need);
     if (hipMemcpyAsync(d_inst, plan->ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
@@ -392,9 +394,20 @@ lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
         return fail(plan, LQT_EHIP, "event creation failed");
     (void)hipEventRecord(plan->ginst_done, s);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
-    hipError_t e = lqt::wave_solve(d_inst, (int)wave.size(), nchunks, nmax, want_fwd, s,
-                                   plan->prof.on ? &hook : nullptr);
-    if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
+    for (size_t j0 = 0; j0 < wave.size();) {
+        size_t j1 = j0;
+        int64_t nch = 0;
+        bool fwd = false;
+        while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
+            nch += plan->ginst_host[j1].NC;
+            fwd = fwd || want_fwd_c[j1];
+            ++j1;
+        }
+        hipError_t e = lqt::tile_solve(cls(wave[j0]), d_inst + j0, (int)(j1 - j0), nch, fwd, s,
+                                       plan->prof.on ? &hook : nullptr);
+        if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
+        j0 = j1;
+    }
     return LQT_OK;
 }
 

@@ -2,25 +2,26 @@
 //
 // One wavefront owns one chunk of B consecutive steps of one instance.  The
 // element being folded and every temporary live in the wavefront's slice of
-// LDS (row-major, leading dimension n + 1 so column walks spread over the
-// banks); the 64 lanes cooperate on every matrix product, factorisation and
-// solve.  All instances of a solve share each launch: the flat chunk index is
-// mapped to its instance by a binary search over the instances' first chunk.
+// LDS; the 64 lanes cooperate on every matrix product, factorisation and
+// solve.  Matrices are zero-padded to a size class N x N (N = 8, 16, 32) so
+// that every loop is unrolled at compile time.  All instances of a size class
+// share each launch: the flat chunk index is mapped to its instance by a
+// binary search over the instances' first chunk.
 //
 // Phases (the reduce-then-scan organisation of the block processing of
 // Section V-C, with the per-instance top level done sequentially -- a batch
 // has far more instances than the GPU has SIMDs):
 //   g_prep    per instance: G (G G^T = L U^{-1} L^T), J = H^T X H, W = H^T X
 //             and the terminal value S_T = H_T^T X_T H_T, v_T = H_T^T X_T r_T;
-//   g_fold    per chunk: fold the one-step elements a_k (Section IV-B) with
+//   t_fold    per chunk: fold the one-step elements a_k (Section IV-B) with
 //             the combination rule (Section IV-A) into the chunk element;
-//   g_chain   per instance: value function at every chunk start, walking the
+//   t_chain   per instance: value function at every chunk start, walking the
 //             chunks from the terminal value with the anchored combination;
-//   g_final   per chunk: down-sweep in Riccati form fused with the gain
+//   t_final   per chunk: down-sweep in Riccati form fused with the gain
 //             extraction (writes S, v, K, d) and the chunk's closed-loop map;
 //   g_fchain  per instance: state at every chunk start from x_0 (Method 1
 //             affine maps, Section IV-C);
-//   g_roll    per chunk: u_k = -K_k x_k + d_k, x_{k+1} = F x_k + c + L u_k.
+//   t_roll    per chunk: u_k = -K_k x_k + d_k, x_{k+1} = F x_k + c + L u_k.
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"
@@ -79,14 +80,6 @@ WDI void wgemv(int R, int K, const double* A, int lda, const double* x, double* 
     wsync();
 }
 
-WDI void wcopy(int R, int Q, const double* A, int lda, double* B, int ldb, int lane) {
-    for (int idx = lane; idx < R * Q; idx += kW) {
-        const int r = idx / Q, q = idx - (idx / Q) * Q;
-        B[r * ldb + q] = A[r * lda + q];
-    }
-    wsync();
-}
-
 // Lower Cholesky factor of the symmetric m x m matrix A, in place (upper
 // triangle zeroed).  Returns false if a pivot is not > 0 (also for NaN).
 WDI bool wchol(int m, double* A, int lda, int lane) {
@@ -118,80 +111,6 @@ WDI void wtrsm_l(int m, int q, const double* R, int ldr, double* B, int ldb, int
             B[i * ldb + c] = s / R[i * ldr + i];
         }
     wsync();
-}
-
-// B (m x q) <- R^{-T} B  (R lower), one column per lane.
-WDI void wtrsm_lt(int m, int q, const double* R, int ldr, double* B, int ldb, int lane) {
-    for (int c = lane; c < q; c += kW)
-        for (int i = m - 1; i >= 0; --i) {
-            double s = B[i * ldb + c];
-            for (int k = i + 1; k < m; ++k) s = fma(-R[k * ldr + i], B[k * ldb + c], s);
-            B[i * ldb + c] = s / R[i * ldr + i];
-        }
-    wsync();
-}
-
-// Mi = M^{-1} by Gauss-Jordan elimination with partial pivoting; M destroyed.
-// A singular M gives non-finite entries (caught by the finiteness checks).
-WDI void winv(int n, double* Mm, int ldm, double* Mi, int ldi, int lane) {
-    for (int idx = lane; idx < n * n; idx += kW) {
-        const int r = idx / n, q = idx - (idx / n) * n;
-        Mi[r * ldi + q] = (r == q) ? 1.0 : 0.0;
-    }
-    wsync();
-    for (int k = 0; k < n; ++k) {
-        // pivot row: largest |M[i][k]|, i >= k (lowest index on ties)
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + lane; i < n; i += kW) {
-            const double v = fabs(Mm[i * ldm + k]);
-            if (v > best) {
-                best = v;
-                bi = i;
-            }
-        }
-        for (int off = kW / 2; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, kW);
-            const int oi = __shfl_xor(bi, off, kW);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        const int p = bi;  // uniform after the butterfly
-        if (p != k) {
-            for (int q = lane; q < n; q += kW) {
-                double t = Mm[k * ldm + q];
-                Mm[k * ldm + q] = Mm[p * ldm + q];
-                Mm[p * ldm + q] = t;
-                t = Mi[k * ldi + q];
-                Mi[k * ldi + q] = Mi[p * ldi + q];
-                Mi[p * ldi + q] = t;
-            }
-            wsync();
-        }
-        const double inv = 1.0 / Mm[k * ldm + k];
-        wsync();  // every lane has read the pivot before row k is scaled
-        for (int q = lane; q < n; q += kW) {
-            Mm[k * ldm + q] *= inv;
-            Mi[k * ldi + q] *= inv;
-        }
-        wsync();
-        // eliminate column k from every other row: one (row, column) pair per
-        // iteration; the multiplier column k of M is updated last, after all
-        // lanes have used it (second pass).
-        for (int idx = lane; idx < n * n; idx += kW) {
-            const int r = idx / n, q = idx - (idx / n) * n;
-            if (r == k) continue;
-            const double fr = Mm[r * ldm + k];
-            Mi[r * ldi + q] = fma(-fr, Mi[k * ldi + q], Mi[r * ldi + q]);
-            if (q != k) Mm[r * ldm + q] = fma(-fr, Mm[k * ldm + q], Mm[r * ldm + q]);
-        }
-        wsync();
-        for (int r = lane; r < n; r += kW)
-            if (r != k) Mm[r * ldm + k] = 0.0;
-        wsync();
-    }
 }
 
 // ---- per-instance descriptor helpers -------------------------------------------
@@ -353,362 +272,6 @@ __global__ __launch_bounds__(kW) void g_prep(const GInst* inst, int ninst, int N
     if (!ok && lane == 0) raise(I.status, 3);
 }
 
-// Step data of a_k into LDS: F (n x n), c (n), G (n x m), eta (n), J (n x n).
-// Time-varying L, U, H, X are factorised here, per step.
-WDI bool load_step(const GInst& I, int64_t k, const double* cst, const CstW& cl, double* Us, double* Ht,
-                   double* Xt, int ld, double* F, double* c, double* G, double* e, double* J, int lane,
-                   bool need_G, bool need_J) {
-    const int n = I.n, m = I.m, p = I.p;
-    const uint32_t ps = I.per_step;
-    bool ok = true;
-    gload(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, ld, lane);
-    for (int q = lane; q < n; q += kW) c[q] = I.c ? step_ptr(I.c, ps, kPS_c, k, n)[q] : 0.0;
-    const double* r = I.r + k * p;
-    if (!(ps & (kPS_L | kPS_U | kPS_H | kPS_X))) {
-        if (need_G) gload(n, m, cst + cl.G, m, G, ld, lane);
-        if (need_J) gload(n, n, cst + cl.J, n, J, ld, lane);
-        for (int q = lane; q < n; q += kW) {
-            double t = 0.0;
-            for (int j = 0; j < p; ++j) t = fma(cst[cl.W + q * p + j], r[j], t);
-            e[q] = t;
-        }
-        wsync();
-    } else {
-        // Us, Ht, Xt: scratch for the per-step factorisations
-        gload(m, m, step_ptr(I.U, ps, kPS_U, k, (int64_t)m * m), m, Us, ld, lane);
-        ok = wchol(m, Us, ld, lane);
-        if (need_G) {
-            const double* L = step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m);
-            for (int idx = lane; idx < m * n; idx += kW) {
-                const int a = idx / n, j = idx - (idx / n) * n;
-                Ht[a * ld + j] = L[j * m + a];
-            }
-            wsync();
-            wtrsm_l(m, n, Us, ld, Ht, ld, lane);
-            for (int idx = lane; idx < n * m; idx += kW) {
-                const int j = idx / m, a = idx - (idx / m) * m;
-                G[j * ld + a] = Ht[a * ld + j];
-            }
-            wsync();
-        }
-        gload(p, n, step_ptr(I.H, ps, kPS_H, k, (int64_t)p * n), n, Ht, ld, lane);
-        gload(p, p, step_ptr(I.X, ps, kPS_X, k, (int64_t)p * p), p, Xt, ld, lane);
-        // W = H^T X into Us (no longer needed)
-        wgemm<true, false>(n, p, p, Ht, ld, Xt, ld, Us, ld, 1.0, 0.0, lane);
-        if (need_J) wgemm<false, false>(n, p, n, Us, ld, Ht, ld, J, ld, 1.0, 0.0, lane, true);
-        for (int q = lane; q < n; q += kW) {
-            double t = 0.0;
-            for (int j = 0; j < p; ++j) t = fma(Us[q * ld + j], r[j], t);
-            e[q] = t;
-        }
-        wsync();
-    }
-    return ok;
-}
-
-// P <- a_k (x) P with C_k = G G^T (matrix inversion lemma form of the
-// combination rule; see the lane-per-element pipeline for the identities).
-// P = (PA, Pb, PC, Pe, PJ) in LDS.  Uses slots 5..9 and vectors 5..9.
-WDI void w_step_combine(int n, int m, const double* F, const double* c, const double* G, const double* ek,
-                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ,
-                        Slots& s, int ld, int lane) {
-    double* Z = s.m[5];    // m x n: G^T J_P, then Y = R^{-1} Z
-    double* Wm = s.m[6];   // m x m: I + Z G, then R
-    double* GtT = s.m[7];  // m x n: R^{-1} G^T
-    double* V = s.m[8];    // n x m: A_P Gt
-    double* T9 = s.m[9];   // n x n scratch
-    double* q = s.v[5];
-    double* g2 = s.v[6];
-    double* w = s.v[7];
-    double* nb = s.v[8];
-    double* ne = s.v[9];
-    wgemm<true, false>(m, n, n, G, ld, PJ, ld, Z, ld, 1.0, 0.0, lane);
-    wgemm<false, false>(m, n, m, Z, ld, G, ld, Wm, ld, 1.0, 0.0, lane, true);
-    for (int a = lane; a < m; a += kW) Wm[a * ld + a] += 1.0;
-    wsync();
-    wchol(m, Wm, ld, lane);  // W >= I: cannot fail for finite inputs
-    wtrsm_l(m, n, Wm, ld, Z, ld, lane);  // Z := Y
-    for (int idx = lane; idx < m * n; idx += kW) {
-        const int a = idx / n, j = idx - (idx / n) * n;
-        GtT[a * ld + j] = G[j * ld + a];
-    }
-    wsync();
-    wtrsm_l(m, n, Wm, ld, GtT, ld, lane);
-    wgemm<false, true>(n, n, m, PA, ld, GtT, ld, V, ld, 1.0, 0.0, lane);  // V = A_P Gt
-    // q = Gt^T eta_P - Y c
-    wgemv<false>(m, n, GtT, ld, Pe, q, 1.0, 0.0, lane);
-    wgemv<false>(m, n, Z, ld, c, q, -1.0, 1.0, lane);
-    // b_new = A_P (c + Gt q) + b_P
-    for (int j = lane; j < n; j += kW) {
-        double t = c[j];
-        for (int a = 0; a < m; ++a) t = fma(GtT[a * ld + j], q[a], t);
-        g2[j] = t;
-    }
-    wsync();
-    wgemv<false>(n, n, PA, ld, g2, nb, 1.0, 0.0, lane);
-    // eta_new = F^T (eta_P - J_P c - Y^T q) + e_k
-    wgemv<false>(n, n, PJ, ld, c, w, -1.0, 0.0, lane);
-    for (int j = lane; j < n; j += kW) {
-        double t = w[j] + Pe[j];
-        for (int a = 0; a < m; ++a) t = fma(-Z[a * ld + j], q[a], t);
-        w[j] = t;
-    }
-    wsync();
-    wgemv<true>(n, n, F, ld, w, ne, 1.0, 0.0, lane);
-    for (int j = lane; j < n; j += kW) {
-        Pb[j] = nb[j] + Pb[j];
-        Pe[j] = ne[j] + ek[j];
-    }
-    // C_new = C_P + V V^T
-    wgemm<false, true>(n, m, n, V, ld, V, ld, PC, ld, 1.0, 1.0, lane, true);
-    // A_new = A_P F - V (Y F)
-    wgemm<false, false>(m, n, n, Z, ld, F, ld, Wm, ld, 1.0, 0.0, lane);   // YF in Wm (R no longer needed)
-    wgemm<false, false>(n, n, n, PA, ld, F, ld, T9, ld, 1.0, 0.0, lane);  // A_P F
-    wgemm<false, false>(n, m, n, V, ld, Wm, ld, T9, ld, -1.0, 1.0, lane);
-    wcopy(n, n, T9, ld, PA, ld, lane);
-    // J_new = F^T (J_P - Y^T Y) F + J_k
-    wgemm<true, false>(n, m, n, Z, ld, Z, ld, PJ, ld, -1.0, 1.0, lane, true);
-    wgemm<false, false>(n, n, n, PJ, ld, F, ld, T9, ld, 1.0, 0.0, lane);
-    wgemm<true, false>(n, n, n, F, ld, T9, ld, PJ, ld, 1.0, 0.0, lane, true);
-    for (int idx = lane; idx < n * n; idx += kW) {
-        const int r = idx / n, q2 = idx - (idx / n) * n;
-        PJ[r * ld + q2] += Js[r * ld + q2];
-    }
-    wsync();
-}
-
-// (S, v) <- E (x) (0, 0, 0, v, S): anchored combination rule.  Uses slots 5..8.
-WDI void w_anchor(int n, const double* EA, const double* Eb, const double* EC, const double* Ee,
-                  const double* EJ, double* Sm, double* v, Slots& s, int ld, int lane) {
-    double* Mm = s.m[5];
-    double* Mi = s.m[6];
-    double* T1 = s.m[7];
-    double* P = s.m[8];
-    double* t = s.v[5];
-    double* nv = s.v[6];
-    wgemm<false, false>(n, n, n, EC, ld, Sm, ld, Mm, ld, 1.0, 0.0, lane);
-    for (int a = lane; a < n; a += kW) Mm[a * ld + a] += 1.0;
-    wsync();
-    winv(n, Mm, ld, Mi, ld, lane);
-    wgemm<false, false>(n, n, n, Mi, ld, EA, ld, T1, ld, 1.0, 0.0, lane);
-    wgemv<false>(n, n, Sm, ld, Eb, t, -1.0, 0.0, lane);
-    for (int j = lane; j < n; j += kW) t[j] += v[j];
-    wsync();
-    wgemv<true>(n, n, T1, ld, t, nv, 1.0, 0.0, lane);
-    wgemm<false, false>(n, n, n, Sm, ld, EA, ld, P, ld, 1.0, 0.0, lane);
-    wgemm<true, false>(n, n, n, T1, ld, P, ld, Sm, ld, 1.0, 0.0, lane, true);
-    for (int idx = lane; idx < n * n; idx += kW) {
-        const int r = idx / n, q = idx - (idx / n) * n;
-        Sm[r * ld + q] += EJ[r * ld + q];
-    }
-    for (int j = lane; j < n; j += kW) v[j] = nv[j] + Ee[j];
-    wsync();
-}
-
-// ---- g_fold ---------------------------------------------------------------------
-
-__global__ __launch_bounds__(kW) void g_fold(const GInst* inst, int ninst, int64_t nchunks, int N) {
-    extern __shared__ __align__(16) double dyn[];
-    const int64_t gc = blockIdx.x;
-    if (gc >= nchunks) return;
-    const int ii = find_instance(inst, ninst, gc);
-    const GInst& I = inst[ii];
-    const int64_t c = gc - I.chunk0;
-    const int lane = threadIdx.x;
-    const int n = I.n, m = I.m;
-    const WaveLds wl = wave_lds(N);
-    const int ld = wl.ld;
-    Slots s = slots_of(dyn, wl);
-    const InstWs ws = inst_ws(I);
-    const CstW cl = cst_layout(n, m, I.p);
-    const int64_t k0 = c * I.B;
-    const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
-    double *PA = s.m[0], *PC = s.m[1], *PJ = s.m[2], *F = s.m[3], *G = s.m[4];
-    double* Js = s.m[10];  // J of the step (constant when time-invariant)
-    double *Pb = s.v[0], *Pe = s.v[1], *cc = s.v[2], *ek = s.v[3];
-    bool ok = true;
-    const bool var = (I.per_step & (kPS_L | kPS_U | kPS_H | kPS_X)) != 0;
-    // slots 5..7 are free while the step data is loaded (step_combine's scratch)
-    ok = load_step(I, k1 - 1, ws.cst, cl, s.m[5], s.m[6], s.m[7], ld, F, cc, G, ek, Js, lane, true, true) && ok;
-    wcopy(n, n, F, ld, PA, ld, lane);
-    wgemm<false, true>(n, m, n, G, ld, G, ld, PC, ld, 1.0, 0.0, lane, true);
-    wcopy(n, n, Js, ld, PJ, ld, lane);
-    for (int j = lane; j < n; j += kW) {
-        Pb[j] = cc[j];
-        Pe[j] = ek[j];
-    }
-    wsync();
-    for (int64_t k = k1 - 2; k >= k0; --k) {
-        ok = load_step(I, k, ws.cst, cl, s.m[5], s.m[6], s.m[7], ld, F, cc, G, ek, Js, lane, var, var) && ok;
-        w_step_combine(n, m, F, cc, G, ek, Js, PA, Pb, PC, Pe, PJ, s, ld, lane);
-    }
-    double* out = ws.agg + c * elem_doubles(n);
-    const int64_t nn = (int64_t)n * n;
-    gstore(n, n, PA, ld, out, n, lane);
-    for (int j = lane; j < n; j += kW) out[nn + j] = Pb[j];
-    gstore(n, n, PC, ld, out + nn + n, n, lane);
-    for (int j = lane; j < n; j += kW) out[2 * nn + n + j] = Pe[j];
-    gstore(n, n, PJ, ld, out + 2 * nn + 2 * n, n, lane);
-    if (!ok && lane == 0) raise(I.status, 3);
-}
-
-// ---- g_chain: value at every chunk start, one wavefront per instance ------------
-
-__global__ __launch_bounds__(kW) void g_chain(const GInst* inst, int ninst, int N) {
-    extern __shared__ __align__(16) double dyn[];
-    const int ii = blockIdx.x;
-    if (ii >= ninst) return;
-    const GInst& I = inst[ii];
-    const int lane = threadIdx.x;
-    const int n = I.n;
-    const WaveLds wl = wave_lds(N);
-    const int ld = wl.ld;
-    Slots s = slots_of(dyn, wl);
-    const InstWs ws = inst_ws(I);
-    const CstW cl = cst_layout(n, I.m, I.p);
-    const int64_t nn = (int64_t)n * n;
-    double *EA = s.m[0], *EC = s.m[1], *EJ = s.m[2], *Sm = s.m[3];
-    double *Eb = s.v[0], *Ee = s.v[1], *v = s.v[2];
-    gload(n, n, ws.cst + cl.ST, n, Sm, ld, lane);
-    for (int j = lane; j < n; j += kW) v[j] = ws.cst[cl.VT + j];
-    wsync();
-    double* vo = ws.val + I.NC * val_doubles(n);
-    gstore(n, n, Sm, ld, vo, n, lane);
-    for (int j = lane; j < n; j += kW) vo[nn + j] = v[j];
-    for (int64_t c = I.NC - 1; c >= 0; --c) {
-        const double* e = ws.agg + c * elem_doubles(n);
-        gload(n, n, e, n, EA, ld, lane);
-        gload(n, n, e + nn + n, n, EC, ld, lane);
-        gload(n, n, e + 2 * nn + 2 * n, n, EJ, ld, lane);
-        for (int j = lane; j < n; j += kW) {
-            Eb[j] = e[nn + j];
-            Ee[j] = e[2 * nn + n + j];
-        }
-        wsync();
-        w_anchor(n, EA, Eb, EC, Ee, EJ, Sm, v, s, ld, lane);
-        vo = ws.val + c * val_doubles(n);
-        gstore(n, n, Sm, ld, vo, n, lane);
-        for (int j = lane; j < n; j += kW) vo[nn + j] = v[j];
-    }
-}
-
-// ---- g_final: down-sweep with gain extraction, chunk closed-loop map -----------
-
-__global__ __launch_bounds__(kW) void g_final(const GInst* inst, int ninst, int64_t nchunks, int N) {
-    extern __shared__ __align__(16) double dyn[];
-    const int64_t gc = blockIdx.x;
-    if (gc >= nchunks) return;
-    const int ii = find_instance(inst, ninst, gc);
-    const GInst& I = inst[ii];
-    const int64_t c = gc - I.chunk0;
-    const int lane = threadIdx.x;
-    const int n = I.n, m = I.m;
-    const WaveLds wl = wave_lds(N);
-    const int ld = wl.ld;
-    Slots s = slots_of(dyn, wl);
-    const InstWs ws = inst_ws(I);
-    const CstW cl = cst_layout(n, m, I.p);
-    const int64_t nn = (int64_t)n * n;
-    const int64_t k0 = c * I.B;
-    const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
-    const uint32_t ps = I.per_step;
-    const bool var = (ps & (kPS_L | kPS_U | kPS_H | kPS_X)) != 0;
-    double *Sm = s.m[0], *F = s.m[1], *L = s.m[2], *Um = s.m[3], *Js = s.m[4];
-    double *SL = s.m[5], *R = s.m[6], *SF = s.m[7], *Y = s.m[8], *K = s.m[9];
-    double *Phi = s.m[10], *Ft = s.m[11], *T12 = s.m[12];
-    double *v = s.v[0], *cc = s.v[1], *ek = s.v[2], *w = s.v[3], *z = s.v[4], *d = s.v[5];
-    double *phi = s.v[6], *ct = s.v[7], *nv = s.v[8], *t9 = s.v[9];
-    // value at the chunk end (= start of chunk c + 1)
-    const double* vin = ws.val + (c + 1) * val_doubles(n);
-    gload(n, n, vin, n, Sm, ld, lane);
-    for (int j = lane; j < n; j += kW) v[j] = vin[nn + j];
-    for (int idx = lane; idx < n * n; idx += kW) {
-        const int r = idx / n, q = idx - (idx / n) * n;
-        Phi[r * ld + q] = (r == q) ? 1.0 : 0.0;
-    }
-    for (int j = lane; j < n; j += kW) phi[j] = 0.0;
-    wsync();
-    if (k1 == I.T) {
-        if (I.S) gstore(n, n, Sm, ld, I.S + I.T * nn, n, lane);
-        if (I.v)
-            for (int j = lane; j < n; j += kW) I.v[I.T * n + j] = v[j];
-    }
-    double fin = 0.0;
-    bool ok = true;
-    for (int64_t k = k1 - 1; k >= k0; --k) {
-        // step data: F, c, L, U, J_k, eta_k
-        // slots 5..7 (SL, R, SF) are free here and serve as scratch
-        ok = load_step(I, k, ws.cst, cl, SL, R, SF, ld, F, cc, T12, ek, Js, lane, false, var || k == k1 - 1) && ok;
-        gload(n, m, step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m), m, L, ld, lane);
-        gload(m, m, step_ptr(I.U, ps, kPS_U, k, (int64_t)m * m), m, Um, ld, lane);
-        // M_k = L^T S L + U = R R^T
-        wgemm<false, false>(n, n, m, Sm, ld, L, ld, SL, ld, 1.0, 0.0, lane);
-        wgemm<true, false>(m, n, m, L, ld, SL, ld, R, ld, 1.0, 0.0, lane, true);
-        for (int idx = lane; idx < m * m; idx += kW) {
-            const int a = idx / m, b = idx - (idx / m) * m;
-            if (b >= a) {
-                const double u = 0.5 * (Um[a * ld + b] + Um[b * ld + a]);
-                R[a * ld + b] += u;
-                if (b != a) R[b * ld + a] += u;
-            }
-        }
-        wsync();
-        ok = wchol(m, R, ld, lane) && ok;
-        // Y = R^{-1} L^T S F ; K = R^{-T} Y
-        wgemm<false, false>(n, n, n, Sm, ld, F, ld, SF, ld, 1.0, 0.0, lane);
-        wgemm<true, false>(m, n, n, L, ld, SF, ld, Y, ld, 1.0, 0.0, lane);
-        wtrsm_l(m, n, R, ld, Y, ld, lane);
-        wcopy(m, n, Y, ld, K, ld, lane);
-        wtrsm_lt(m, n, R, ld, K, ld, lane);
-        // w = v - S c ; z = L^T w ; d = M^{-1} z
-        wgemv<false>(n, n, Sm, ld, cc, w, -1.0, 0.0, lane);
-        for (int j = lane; j < n; j += kW) w[j] += v[j];
-        wsync();
-        wgemv<true>(m, n, L, ld, w, z, 1.0, 0.0, lane);
-        for (int a = lane; a < m; a += kW) d[a] = z[a];
-        wsync();
-        wtrsm_l(m, 1, R, ld, d, 1, lane);
-        wtrsm_lt(m, 1, R, ld, d, 1, lane);
-        // S' = F^T S F - Y^T Y + J ; v' = F^T w - K^T z + eta
-        wgemm<true, false>(n, n, n, F, ld, SF, ld, T12, ld, 1.0, 0.0, lane, true);
-        wgemm<true, false>(n, m, n, Y, ld, Y, ld, T12, ld, -1.0, 1.0, lane, true);
-        wgemv<true>(n, n, F, ld, w, nv, 1.0, 0.0, lane);
-        wgemv<true>(n, m, K, ld, z, nv, -1.0, 1.0, lane);
-        for (int idx = lane; idx < n * n; idx += kW) {
-            const int r = idx / n, q = idx - (idx / n) * n;
-            Sm[r * ld + q] = T12[r * ld + q] + Js[r * ld + q];
-        }
-        for (int j = lane; j < n; j += kW) v[j] = nv[j] + ek[j];
-        wsync();
-        // Ft = F - L K ; ct = c + L d
-        wcopy(n, n, F, ld, Ft, ld, lane);
-        wgemm<false, false>(n, m, n, L, ld, K, ld, Ft, ld, -1.0, 1.0, lane);
-        wgemv<false>(n, m, L, ld, d, ct, 1.0, 0.0, lane);
-        for (int j = lane; j < n; j += kW) ct[j] += cc[j];
-        wsync();
-        // outputs (contiguous rows, coalesced across the wavefront)
-        if (I.S) gstore(n, n, Sm, ld, I.S + k * nn, n, lane);
-        if (I.v)
-            for (int j = lane; j < n; j += kW) I.v[k * n + j] = v[j];
-        gstore(m, n, K, ld, I.K + k * m * n, n, lane);
-        for (int a = lane; a < m; a += kW) I.d[k * m + a] = d[a];
-        for (int idx = lane; idx < n * n; idx += kW) fin += Sm[(idx / n) * ld + (idx % n)];
-        for (int j = lane; j < n; j += kW) fin += v[j];
-        // chunk map: Phi <- Phi Ft, phi <- Phi ct + phi
-        wgemv<false>(n, n, Phi, ld, ct, t9, 1.0, 0.0, lane);
-        for (int j = lane; j < n; j += kW) phi[j] += t9[j];
-        wgemm<false, false>(n, n, n, Phi, ld, Ft, ld, T12, ld, 1.0, 0.0, lane);
-        wcopy(n, n, T12, ld, Phi, ld, lane);
-    }
-    double* mo = ws.map + c * val_doubles(n);
-    gstore(n, n, Phi, ld, mo, n, lane);
-    for (int j = lane; j < n; j += kW) mo[nn + j] = phi[j];
-    // any lane's non-finite partial sum marks the instance
-    const bool bad = !isfinite(fin);
-    if (__any(bad) && lane == 0) raise(I.status, 4);
-    if (!ok && lane == 0) raise(I.status, 3);
-}
-
 // ---- forward pass ------------------------------------------------------------------
 
 __global__ __launch_bounds__(kW) void g_fchain(const GInst* inst, int ninst, int N) {
@@ -740,57 +303,709 @@ __global__ __launch_bounds__(kW) void g_fchain(const GInst* inst, int ninst, int
     }
 }
 
-__global__ __launch_bounds__(kW) void g_roll(const GInst* inst, int ninst, int64_t nchunks, int N) {
+// ============================================================================
+// Size-class kernels: every matrix is zero-padded to a compile-time N x N
+// (N = 8, 16, 32), so all loops unroll and each lane owns a fixed output tile
+// of every product (an 8 x 8 grid of tiles covers the N x N result).  The
+// padding is exact: F, G, L, J, S, C, x are zero outside the n / m block, and
+// every matrix that is factorised or inverted (U, I + G^T J G, I + C S,
+// L^T S L + U) is the identity there.
+// ============================================================================
+
+template <int N>
+struct TL {
+    static constexpr int ld = N + 2;   // 16-byte aligned rows, rows spread over the banks
+    static constexpr int mat = N * ld;
+    static constexpr int T = N / 8;    // per-lane output tile is T x T
+};
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+// C = alpha op(A) op(B) + beta C on the matrix cores (N = 16, 32): 16 x 16
+// output tiles, 16 x 16 x 4 FP64 MFMA per k-slice.  Operand layout (measured
+// on gfx950): lane l supplies A[l % 16][4s + l / 16] and B[4s + l / 16][l % 16];
+// accumulator element v of lane l is C[l / 16 + 4 v][l % 16].
+template <int N, bool TA, bool TB, bool SYM>
+WDI void tgemm_mfma(const double* A, const double* B, double* C, double alpha, double beta, int lane) {
+    constexpr int ld = TL<N>::ld, NT = N / 16;
+    const int i0 = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int bi = 0; bi < NT; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NT; ++bj) {
+            if (SYM && bi > bj) continue;
+            dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < N / 4; ++s4) {
+                const int kx = 4 * s4 + kk;
+                const int ar = 16 * bi + i0, bc = 16 * bj + i0;
+                const double a = TA ? A[kx * ld + ar] : A[ar * ld + kx];
+                const double b = TB ? B[bc * ld + kx] : B[kx * ld + bc];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            double out[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + kk + 4 * v, c = 16 * bj + i0;
+                out[v] = (beta == 0.0) ? alpha * acc[v] : fma(alpha, acc[v], beta * C[r * ld + c]);
+            }
+            // every lane has read its C inputs before any tile entry is written
+            if (SYM) wsync();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + kk + 4 * v, c = 16 * bj + i0;
+                if (SYM && r > c) continue;  // written as the mirror of (c, r)
+                C[r * ld + c] = out[v];
+                if (SYM) C[c * ld + r] = out[v];
+            }
+        }
+    wsync();
+}
+
+// C = alpha op(A) op(B) + beta C, all N x N.  sym: the result is symmetric;
+// only tiles on or above the diagonal are computed and each value is written
+// to both mirrored positions (exactly symmetric).
+template <int N, bool TA, bool TB, bool SYM = false>
+WDI void tgemm(const double* A, const double* B, double* C, double alpha, double beta, int lane) {
+    if constexpr (N >= 16) {
+        tgemm_mfma<N, TA, TB, SYM>(A, B, C, alpha, beta, lane);
+        return;
+    }
+    constexpr int ld = TL<N>::ld, T = TL<N>::T;
+    const int tr = lane >> 3, tc = lane & 7;
+    const int r0 = tr * T, c0 = tc * T;
+    if (!(SYM && tr > tc)) {
+        double acc[T][T];
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j) acc[i][j] = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < N; ++k) {
+            double a[T], b[T];
+#pragma unroll
+            for (int i = 0; i < T; ++i) a[i] = TA ? A[k * ld + r0 + i] : A[(r0 + i) * ld + k];
+#pragma unroll
+            for (int j = 0; j < T; ++j) b[j] = TB ? B[(c0 + j) * ld + k] : B[k * ld + c0 + j];
+#pragma unroll
+            for (int i = 0; i < T; ++i)
+#pragma unroll
+                for (int j = 0; j < T; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        double out[T][T];
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j)
+                out[i][j] = (beta == 0.0) ? alpha * acc[i][j] : fma(alpha, acc[i][j], beta * C[(r0 + i) * ld + c0 + j]);
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                if (SYM && tr == tc && j < i) continue;  // lower part of a diagonal tile: mirror of (j, i)
+                C[(r0 + i) * ld + c0 + j] = out[i][j];
+                if (SYM) C[(c0 + j) * ld + r0 + i] = out[i][j];
+            }
+    }
+    wsync();
+}
+
+// y = alpha op(A) x + beta y (N x N, vectors of N)
+template <int N, bool TA>
+WDI void tgemv(const double* A, const double* x, double* y, double alpha, double beta, int lane) {
+    constexpr int ld = TL<N>::ld;
+    if (lane < N) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(TA ? A[k * ld + lane] : A[lane * ld + k], x[k], s);
+        y[lane] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[lane]);
+    }
+    wsync();
+}
+
+template <int N>
+WDI void tcopy(const double* A, double* B, int lane) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < N * N; idx += kW) B[(idx / N) * ld + (idx % N)] = A[(idx / N) * ld + (idx % N)];
+    wsync();
+}
+
+template <int N>
+WDI void tzero(double* A, int lane) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < N * N; idx += kW) A[(idx / N) * ld + (idx % N)] = 0.0;
+    wsync();
+}
+
+// Lower Cholesky factor in place; upper triangle zeroed.
+template <int N>
+WDI bool tchol(double* A, int lane) {
+    constexpr int ld = TL<N>::ld;
+    bool ok = true;
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+        double s = A[j * ld + j];
+        for (int k = 0; k < j; ++k) s = fma(-A[j * ld + k], A[j * ld + k], s);
+        ok = ok && (s > 0.0);
+        const double rjj = sqrt(s);
+        const double rinv = 1.0 / rjj;
+        wsync();
+        if (lane == j) A[j * ld + j] = rjj;
+        if (lane > j && lane < N) {
+            double t = A[lane * ld + j];
+            for (int k = 0; k < j; ++k) t = fma(-A[lane * ld + k], A[j * ld + k], t);
+            A[lane * ld + j] = t * rinv;
+        }
+        if (lane < j) A[lane * ld + j] = 0.0;
+        wsync();
+    }
+    return ok;
+}
+
+// B <- R^{-1} B (R lower, N x N); lane c updates column c in place.
+template <int N>
+WDI void ttrsm_l(const double* R, double* B, int lane) {
+    constexpr int ld = TL<N>::ld;
+    if (lane < N) {
+#pragma unroll 1
+        for (int i = 0; i < N; ++i) {
+            double s = B[i * ld + lane];
+#pragma unroll 4
+            for (int k = 0; k < i; ++k) s = fma(-R[i * ld + k], B[k * ld + lane], s);
+            B[i * ld + lane] = s / R[i * ld + i];
+        }
+    }
+    wsync();
+}
+
+// Ai = A^{-1} for a symmetric positive definite A (Gauss-Jordan without
+// pivoting: the pivots of an SPD matrix are positive).  Only the leading m x m
+// block is eliminated; the padded block is the identity and stays so.  A is
+// destroyed.  Returns false if a pivot is not > 0 (including NaN).
+template <int N>
+WDI bool tspdinv(double* A, double* Ai, int m, int lane) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < N * N; idx += kW) {
+        const int r = idx / N, q = idx % N;
+        Ai[r * ld + q] = (r == q) ? 1.0 : 0.0;
+    }
+    wsync();
+    bool ok = true;
+#pragma unroll 1
+    for (int k = 0; k < m; ++k) {
+        const double piv = A[k * ld + k];
+        ok = ok && (piv > 0.0);
+        const double inv = 1.0 / piv;
+        wsync();
+        if (lane < m) {
+            A[k * ld + lane] *= inv;
+            Ai[k * ld + lane] *= inv;
+        }
+        wsync();
+        for (int idx = lane; idx < m * m; idx += kW) {
+            const int r = idx / m, q = idx - (idx / m) * m;
+            if (r == k) continue;
+            const double fr = A[r * ld + k];
+            Ai[r * ld + q] = fma(-fr, Ai[k * ld + q], Ai[r * ld + q]);
+            if (q != k) A[r * ld + q] = fma(-fr, A[k * ld + q], A[r * ld + q]);
+        }
+        wsync();
+        if (lane < m && lane != k) A[lane * ld + k] = 0.0;
+        wsync();
+    }
+    return ok;
+}
+
+// Mi = M^{-1}, Gauss-Jordan with partial pivoting (M destroyed).
+template <int N>
+WDI void tinv(double* Mm, double* Mi, int lane) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < N * N; idx += kW) {
+        const int r = idx / N, q = idx % N;
+        Mi[r * ld + q] = (r == q) ? 1.0 : 0.0;
+    }
+    wsync();
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double best = -1.0;
+        int bi = k;
+        if (lane >= k && lane < N) {
+            best = fabs(Mm[lane * ld + k]);
+            bi = lane;
+        }
+        for (int off = kW / 2; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, kW);
+            const int oi = __shfl_xor(bi, off, kW);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        const int p = bi;
+        if (p != k) {
+            if (lane < N) {
+                double t = Mm[k * ld + lane];
+                Mm[k * ld + lane] = Mm[p * ld + lane];
+                Mm[p * ld + lane] = t;
+                t = Mi[k * ld + lane];
+                Mi[k * ld + lane] = Mi[p * ld + lane];
+                Mi[p * ld + lane] = t;
+            }
+            wsync();
+        }
+        const double inv = 1.0 / Mm[k * ld + k];
+        wsync();
+        if (lane < N) {
+            Mm[k * ld + lane] *= inv;
+            Mi[k * ld + lane] *= inv;
+        }
+        wsync();
+        for (int idx = lane; idx < N * N; idx += kW) {
+            const int r = idx / N, q = idx % N;
+            if (r == k) continue;
+            const double fr = Mm[r * ld + k];
+            Mi[r * ld + q] = fma(-fr, Mi[k * ld + q], Mi[r * ld + q]);
+            if (q != k) Mm[r * ld + q] = fma(-fr, Mm[k * ld + q], Mm[r * ld + q]);
+        }
+        wsync();
+        if (lane < N && lane != k) Mm[lane * ld + k] = 0.0;
+        wsync();
+    }
+}
+
+// global (R x Q, row stride gq) -> LDS N x N, zero padded; `diag` on the
+// padded diagonal (1 for matrices that are factorised).
+template <int N>
+WDI void tload(int R, int Q, const double* g, int gq, double* l, int lane, double diag = 0.0) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < N * N; idx += kW) {
+        const int r = idx / N, q = idx % N;
+        l[r * ld + q] = (r < R && q < Q) ? g[r * gq + q] : ((r == q && r >= R) ? diag : 0.0);
+    }
+    wsync();
+}
+
+template <int N>
+WDI void tstore(int R, int Q, const double* l, double* g, int gq, int lane) {
+    constexpr int ld = TL<N>::ld;
+    for (int idx = lane; idx < R * Q; idx += kW) {
+        const int r = idx / Q, q = idx - (idx / Q) * Q;
+        g[r * gq + q] = l[r * ld + q];
+    }
+}
+
+template <int N>
+struct TSlots {
+    double* m[14];
+    double* v[12];
+    static constexpr int doubles() { return 14 * TL<N>::mat + 12 * (N + 2); }
+};
+
+template <int N>
+WDI TSlots<N> tslots(double* base) {
+    TSlots<N> s;
+#pragma unroll
+    for (int i = 0; i < 14; ++i) s.m[i] = base + i * TL<N>::mat;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s.v[i] = base + 14 * TL<N>::mat + i * (N + 2);
+    return s;
+}
+
+// eta_k = W r_k (W = H^T X in LDS, n x p zero padded, p <= N).
+template <int N>
+WDI void teta(const double* W, const double* rk, int p, double* e, int lane) {
+    constexpr int ld = TL<N>::ld;
+    if (lane < N) {
+        double s = 0.0;
+        for (int j = 0; j < p; ++j) s = fma(W[lane * ld + j], rk[j], s);
+        e[lane] = s;
+    }
+    wsync();
+}
+
+// Step data for a time-varying step k (any of L, U, H, X per step): G_k,
+// J_k and eta_k computed from the step's matrices (p <= N).
+template <int N>
+WDI bool tstep_var(const GInst& I, int64_t k, double* Us, double* Ht, double* Xt, double* G, double* J, double* e,
+                   bool need_G, int lane) {
+    constexpr int ld = TL<N>::ld;
+    const int n = I.n, m = I.m, p = I.p;
+    const uint32_t ps = I.per_step;
+    tload<N>(m, m, step_ptr(I.U, ps, kPS_U, k, (int64_t)m * m), m, Us, lane, 1.0);
+    const bool ok = tchol<N>(Us, lane);
+    if (need_G) {
+        const double* L = step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m);
+        for (int idx = lane; idx < N * N; idx += kW) {  // Ht := L^T (zero padded)
+            const int a = idx / N, j = idx % N;
+            Ht[a * ld + j] = (a < m && j < n) ? L[j * m + a] : 0.0;
+        }
+        wsync();
+        ttrsm_l<N>(Us, Ht, lane);
+        for (int idx = lane; idx < N * N; idx += kW) {
+            const int j = idx / N, a = idx % N;
+            G[j * ld + a] = Ht[a * ld + j];
+        }
+        wsync();
+    }
+    tload<N>(p, n, step_ptr(I.H, ps, kPS_H, k, (int64_t)p * n), n, Ht, lane);
+    tload<N>(p, p, step_ptr(I.X, ps, kPS_X, k, (int64_t)p * p), p, Xt, lane);
+    tgemm<N, true, false>(Ht, Xt, Us, 1.0, 0.0, lane);  // W = H^T X
+    tgemm<N, false, false, true>(Us, Ht, J, 1.0, 0.0, lane);
+    if (lane < N) {
+        double s = 0.0;
+        const double* r = I.r + k * p;
+        for (int j = 0; j < p; ++j) s = fma(Us[lane * ld + j], r[j], s);
+        e[lane] = s;
+    }
+    wsync();
+    return ok;
+}
+
+template <int N>
+WDI void tvec_load(int n, const double* g, double* l, int lane) {
+    if (lane < N) l[lane] = (lane < n) ? g[lane] : 0.0;
+    wsync();
+}
+
+// P <- a_k (x) P, matrix inversion lemma form of the combination rule with
+// C_k = G G^T: W = I + G^T J_P G (m x m SPD) and, with Z = G^T J_P,
+//   (I + C_k J_P)^{-1} = I - G W^{-1} Z,
+//   A' = A_P F - (A_P G) W^{-1} Z F,   C' = C_P + (A_P G) W^{-1} (A_P G)^T,
+//   b' = A_P (c + G h) + b_P,          eta' = F^T (eta_P - J_P c - Z^T h) + eta_k,
+//   J' = F^T (J_P - Z^T W^{-1} Z) F + J_k,   h = W^{-1} (G^T eta_P - Z c).
+template <int N>
+WDI void t_step_combine(int m, const double* F, const double* c, const double* G, const double* ek,
+                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, TSlots<N>& s,
+                        int lane) {
+    constexpr int ld = TL<N>::ld;
+    double* Z = s.m[7];
+    double* Wm = s.m[8];
+    double* Wi = s.m[9];
+    double* AG = s.m[10];
+    double* T9 = s.m[11];
+    double* X1 = s.m[12];
+    double *h = s.v[5], *hw = s.v[6], *w = s.v[7], *nb = s.v[8], *ne = s.v[9];
+    tgemm<N, true, false>(G, PJ, Z, 1.0, 0.0, lane);               // Z = G^T J_P
+    tgemm<N, false, false, true>(Z, G, Wm, 1.0, 0.0, lane);        // Z G
+    if (lane < N) Wm[lane * ld + lane] += 1.0;
+    wsync();
+    tspdinv<N>(Wm, Wi, m, lane);                                   // W >= I: always SPD
+    tgemm<N, false, false>(Wi, Z, X1, 1.0, 0.0, lane);             // W^{-1} Z
+    tgemm<N, false, false>(PA, G, AG, 1.0, 0.0, lane);             // A_P G
+    // h = W^{-1} (G^T eta_P - Z c)
+    tgemv<N, true>(G, Pe, h, 1.0, 0.0, lane);
+    tgemv<N, false>(Z, c, h, -1.0, 1.0, lane);
+    tgemv<N, false>(Wi, h, hw, 1.0, 0.0, lane);
+    // b' = A_P (c + G h) + b_P
+    tgemv<N, false>(G, hw, w, 1.0, 0.0, lane);
+    if (lane < N) w[lane] += c[lane];
+    wsync();
+    tgemv<N, false>(PA, w, nb, 1.0, 0.0, lane);
+    // eta' = F^T (eta_P - J_P c - Z^T h) + eta_k
+    tgemv<N, false>(PJ, c, w, -1.0, 0.0, lane);
+    tgemv<N, true>(Z, hw, h, 1.0, 0.0, lane);
+    if (lane < N) w[lane] += Pe[lane] - h[lane];
+    wsync();
+    tgemv<N, true>(F, w, ne, 1.0, 0.0, lane);
+    if (lane < N) {
+        Pb[lane] += nb[lane];
+        Pe[lane] = ne[lane] + ek[lane];
+    }
+    wsync();
+    // C' = C_P + (A_P G) W^{-1} (A_P G)^T
+    tgemm<N, false, false>(AG, Wi, T9, 1.0, 0.0, lane);
+    tgemm<N, false, true, true>(T9, AG, PC, 1.0, 1.0, lane);
+    // A' = A_P F - (A_P G)(W^{-1} Z F)
+    tgemm<N, false, false>(X1, F, Wm, 1.0, 0.0, lane);
+    tgemm<N, false, false>(PA, F, T9, 1.0, 0.0, lane);
+    tgemm<N, false, false>(AG, Wm, T9, -1.0, 1.0, lane);
+    tcopy<N>(T9, PA, lane);
+    // J' = F^T (J_P - Z^T W^{-1} Z) F + J_k
+    tgemm<N, true, false, true>(Z, X1, PJ, -1.0, 1.0, lane);
+    tgemm<N, false, false>(PJ, F, T9, 1.0, 0.0, lane);
+    tgemm<N, true, false, true>(F, T9, PJ, 1.0, 0.0, lane);
+    for (int idx = lane; idx < N * N; idx += kW) PJ[(idx / N) * ld + idx % N] += Js[(idx / N) * ld + idx % N];
+    wsync();
+}
+
+template <int N>
+__global__ __launch_bounds__(kW) void t_fold(const GInst* inst, int ninst, int64_t nchunks) {
     extern __shared__ __align__(16) double dyn[];
     const int64_t gc = blockIdx.x;
     if (gc >= nchunks) return;
-    const int ii = find_instance(inst, ninst, gc);
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
+    const int64_t c = gc - I.chunk0;
+    const int lane = threadIdx.x;
+    const int n = I.n, m = I.m, p = I.p;
+    TSlots<N> s = tslots<N>(dyn);
+    const InstWs ws = inst_ws(I);
+    const CstW cl = cst_layout(n, m, p);
+    const int64_t k0 = c * I.B;
+    const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
+    const uint32_t ps = I.per_step;
+    const bool var = (ps & (kPS_L | kPS_U | kPS_H | kPS_X)) != 0;
+    double *PA = s.m[0], *PC = s.m[1], *PJ = s.m[2], *F = s.m[3], *G = s.m[4], *Js = s.m[5], *W = s.m[6];
+    double *Pb = s.v[0], *Pe = s.v[1], *cc = s.v[2], *ek = s.v[3], *rk = s.v[4];
+    bool ok = true;
+    if (!var) {
+        tload<N>(n, m, ws.cst + cl.G, m, G, lane);
+        tload<N>(n, n, ws.cst + cl.J, n, Js, lane);
+        tload<N>(n, p, ws.cst + cl.W, p, W, lane);
+    }
+    auto step_data = [&](int64_t k, bool first) {
+        if (first || (ps & kPS_F)) tload<N>(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, lane);
+        if (first || (ps & kPS_c)) {
+            if (lane < N) cc[lane] = (I.c && lane < n) ? step_ptr(I.c, ps, kPS_c, k, n)[lane] : 0.0;
+            wsync();
+        }
+        if (var) {
+            // scratch: T9 (11), V (10), GtT (9) are free between combines
+            ok = tstep_var<N>(I, k, s.m[9], s.m[10], s.m[11], G, Js, ek, true, lane) && ok;
+        } else {
+            if (lane < p) rk[lane] = I.r[k * p + lane];
+            wsync();
+            teta<N>(W, rk, p, ek, lane);
+        }
+    };
+    step_data(k1 - 1, true);
+    tcopy<N>(F, PA, lane);
+    tgemm<N, false, true, true>(G, G, PC, 1.0, 0.0, lane);
+    tcopy<N>(Js, PJ, lane);
+    if (lane < N) {
+        Pb[lane] = cc[lane];
+        Pe[lane] = ek[lane];
+    }
+    wsync();
+#pragma unroll 1
+    for (int64_t k = k1 - 2; k >= k0; --k) {
+        step_data(k, false);
+        t_step_combine<N>(m, F, cc, G, ek, Js, PA, Pb, PC, Pe, PJ, s, lane);
+    }
+    double* out = ws.agg + c * elem_doubles(n);
+    const int64_t nn = (int64_t)n * n;
+    tstore<N>(n, n, PA, out, n, lane);
+    if (lane < n) out[nn + lane] = Pb[lane];
+    tstore<N>(n, n, PC, out + nn + n, n, lane);
+    if (lane < n) out[2 * nn + n + lane] = Pe[lane];
+    tstore<N>(n, n, PJ, out + 2 * nn + 2 * n, n, lane);
+    if (!ok && lane == 0) raise(I.status, 3);
+}
+
+// Value functions at every chunk start, one wavefront per instance.
+template <int N>
+__global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
+    extern __shared__ __align__(16) double dyn[];
+    const int ii = blockIdx.x;
+    if (ii >= ninst) return;
     const GInst& I = inst[ii];
+    const int lane = threadIdx.x;
+    const int n = I.n;
+    TSlots<N> s = tslots<N>(dyn);
+    const InstWs ws = inst_ws(I);
+    const CstW cl = cst_layout(n, I.m, I.p);
+    const int64_t nn = (int64_t)n * n;
+    double *EA = s.m[0], *EC = s.m[1], *EJ = s.m[2], *Sm = s.m[3];
+    double *Mm = s.m[4], *Mi = s.m[5], *T1 = s.m[6], *P = s.m[7];
+    double *Eb = s.v[0], *Ee = s.v[1], *v = s.v[2], *t = s.v[3], *nv = s.v[4];
+    tload<N>(n, n, ws.cst + cl.ST, n, Sm, lane);
+    tvec_load<N>(n, ws.cst + cl.VT, v, lane);
+    double* vo = ws.val + I.NC * val_doubles(n);
+    tstore<N>(n, n, Sm, vo, n, lane);
+    if (lane < n) vo[nn + lane] = v[lane];
+#pragma unroll 1
+    for (int64_t c = I.NC - 1; c >= 0; --c) {
+        const double* e = ws.agg + c * elem_doubles(n);
+        tload<N>(n, n, e, n, EA, lane);
+        tload<N>(n, n, e + nn + n, n, EC, lane);
+        tload<N>(n, n, e + 2 * nn + 2 * n, n, EJ, lane);
+        tvec_load<N>(n, e + nn, Eb, lane);
+        tvec_load<N>(n, e + 2 * nn + n, Ee, lane);
+        // (S, v) <- E (x) (0, 0, 0, v, S)
+        tgemm<N, false, false>(EC, Sm, Mm, 1.0, 0.0, lane);
+        if (lane < N) Mm[lane * TL<N>::ld + lane] += 1.0;
+        wsync();
+        tinv<N>(Mm, Mi, lane);
+        tgemm<N, false, false>(Mi, EA, T1, 1.0, 0.0, lane);
+        tgemv<N, false>(Sm, Eb, t, -1.0, 0.0, lane);
+        if (lane < N) t[lane] += v[lane];
+        wsync();
+        tgemv<N, true>(T1, t, nv, 1.0, 0.0, lane);
+        tgemm<N, false, false>(Sm, EA, P, 1.0, 0.0, lane);
+        tgemm<N, true, false, true>(T1, P, Sm, 1.0, 0.0, lane);
+        for (int idx = lane; idx < N * N; idx += kW)
+            Sm[(idx / N) * TL<N>::ld + idx % N] += EJ[(idx / N) * TL<N>::ld + idx % N];
+        if (lane < N) v[lane] = nv[lane] + Ee[lane];
+        wsync();
+        vo = ws.val + c * val_doubles(n);
+        tstore<N>(n, n, Sm, vo, n, lane);
+        if (lane < n) vo[nn + lane] = v[lane];
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int64_t nchunks) {
+    extern __shared__ __align__(16) double dyn[];
+    constexpr int ld = TL<N>::ld;
+    const int64_t gc = blockIdx.x;
+    if (gc >= nchunks) return;
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
+    const int64_t c = gc - I.chunk0;
+    const int lane = threadIdx.x;
+    const int n = I.n, m = I.m, p = I.p;
+    TSlots<N> s = tslots<N>(dyn);
+    const InstWs ws = inst_ws(I);
+    const CstW cl = cst_layout(n, m, p);
+    const int64_t nn = (int64_t)n * n;
+    const int64_t k0 = c * I.B;
+    const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
+    const uint32_t ps = I.per_step;
+    const bool var = (ps & (kPS_L | kPS_U | kPS_H | kPS_X)) != 0;
+    double *Sm = s.m[0], *F = s.m[1], *L = s.m[2], *Um = s.m[3], *Js = s.m[4], *W = s.m[5];
+    double *SL = s.m[6], *R = s.m[7], *SF = s.m[8], *Y = s.m[9], *K = s.m[10];
+    double *Phi = s.m[11], *Ft = s.m[12], *T13 = s.m[13];
+    double *v = s.v[0], *cc = s.v[1], *ek = s.v[2], *w = s.v[3], *z = s.v[4], *d = s.v[5];
+    double *phi = s.v[6], *ct = s.v[7], *nv = s.v[8], *t9 = s.v[9], *rk = s.v[10];
+    const double* vin = ws.val + (c + 1) * val_doubles(n);
+    tload<N>(n, n, vin, n, Sm, lane);
+    tvec_load<N>(n, vin + nn, v, lane);
+    for (int idx = lane; idx < N * N; idx += kW) Phi[(idx / N) * ld + idx % N] = ((idx / N) == (idx % N)) ? 1.0 : 0.0;
+    if (lane < N) phi[lane] = 0.0;
+    wsync();
+    if (!var) {
+        tload<N>(n, n, ws.cst + cl.J, n, Js, lane);
+        tload<N>(n, p, ws.cst + cl.W, p, W, lane);
+    }
+    if (k1 == I.T) {
+        if (I.S) tstore<N>(n, n, Sm, I.S + I.T * nn, n, lane);
+        if (I.v && lane < n) I.v[I.T * n + lane] = v[lane];
+    }
+    double fin = 0.0;
+    bool ok = true;
+#pragma unroll 1
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+        const bool first = (k == k1 - 1);
+        if (first || (ps & kPS_F)) tload<N>(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, lane);
+        if (first || (ps & kPS_L)) tload<N>(n, m, step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m), m, L, lane);
+        if (first || (ps & kPS_U)) tload<N>(m, m, step_ptr(I.U, ps, kPS_U, k, (int64_t)m * m), m, Um, lane, 1.0);
+        if (first || (ps & kPS_c)) {
+            if (lane < N) cc[lane] = (I.c && lane < n) ? step_ptr(I.c, ps, kPS_c, k, n)[lane] : 0.0;
+            wsync();
+        }
+        if (var) {
+            ok = tstep_var<N>(I, k, SL, R, SF, T13, Js, ek, false, lane) && ok;
+        } else {
+            if (lane < p) rk[lane] = I.r[k * p + lane];
+            wsync();
+            teta<N>(W, rk, p, ek, lane);
+        }
+        // M_k = L^T S L + U, inverted (SPD)
+        tgemm<N, false, false>(Sm, L, SL, 1.0, 0.0, lane);
+        for (int idx = lane; idx < N * N; idx += kW) {  // symmetrised U (identity on the padding)
+            const int a = idx / N, b = idx % N;
+            R[a * ld + b] = 0.5 * (Um[a * ld + b] + Um[b * ld + a]);
+        }
+        wsync();
+        tgemm<N, true, false, true>(L, SL, R, 1.0, 1.0, lane);
+        ok = tspdinv<N>(R, Y, m, lane) && ok;                      // Y := M_k^{-1}
+        // K = M^{-1} L^T S F ; P = L^T S F in SL
+        tgemm<N, false, false>(Sm, F, SF, 1.0, 0.0, lane);
+        tgemm<N, true, false>(L, SF, SL, 1.0, 0.0, lane);
+        tgemm<N, false, false>(Y, SL, K, 1.0, 0.0, lane);
+        // w = v - S c ; z = L^T w ; d = M^{-1} z
+        tgemv<N, false>(Sm, cc, w, -1.0, 0.0, lane);
+        if (lane < N) w[lane] += v[lane];
+        wsync();
+        tgemv<N, true>(L, w, z, 1.0, 0.0, lane);
+        tgemv<N, false>(Y, z, d, 1.0, 0.0, lane);
+        // S' = F^T S F - P^T K + J ; v' = F^T w - K^T z + eta
+        tgemm<N, true, false, true>(F, SF, T13, 1.0, 0.0, lane);
+        tgemm<N, true, false, true>(SL, K, T13, -1.0, 1.0, lane);
+        tgemv<N, true>(F, w, nv, 1.0, 0.0, lane);
+        tgemv<N, true>(K, z, nv, -1.0, 1.0, lane);
+        for (int idx = lane; idx < N * N; idx += kW)
+            Sm[(idx / N) * ld + idx % N] = T13[(idx / N) * ld + idx % N] + Js[(idx / N) * ld + idx % N];
+        if (lane < N) v[lane] = nv[lane] + ek[lane];
+        wsync();
+        tcopy<N>(F, Ft, lane);
+        tgemm<N, false, false>(L, K, Ft, -1.0, 1.0, lane);
+        tgemv<N, false>(L, d, ct, 1.0, 0.0, lane);
+        if (lane < N) ct[lane] += cc[lane];
+        wsync();
+        if (I.S) tstore<N>(n, n, Sm, I.S + k * nn, n, lane);
+        if (I.v && lane < n) I.v[k * n + lane] = v[lane];
+        tstore<N>(m, n, K, I.K + k * m * n, n, lane);
+        if (lane < m) I.d[k * m + lane] = d[lane];
+        for (int idx = lane; idx < n * n; idx += kW) fin += Sm[(idx / n) * ld + idx % n];
+        if (lane < n) fin += v[lane];
+        tgemv<N, false>(Phi, ct, t9, 1.0, 0.0, lane);
+        if (lane < N) phi[lane] += t9[lane];
+        wsync();
+        tgemm<N, false, false>(Phi, Ft, T13, 1.0, 0.0, lane);
+        tcopy<N>(T13, Phi, lane);
+    }
+    double* mo = ws.map + c * val_doubles(n);
+    tstore<N>(n, n, Phi, mo, n, lane);
+    if (lane < n) mo[nn + lane] = phi[lane];
+    if (__any(!isfinite(fin)) && lane == 0) raise(I.status, 4);
+    if (!ok && lane == 0) raise(I.status, 3);
+}
+
+template <int N>
+__global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64_t nchunks) {
+    extern __shared__ __align__(16) double dyn[];
+    constexpr int ld = TL<N>::ld;
+    const int64_t gc = blockIdx.x;
+    if (gc >= nchunks) return;
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
     const int lane = threadIdx.x;
     const int n = I.n, m = I.m;
-    const WaveLds wl = wave_lds(N);
-    const int ld = wl.ld;
-    Slots s = slots_of(dyn, wl);
+    TSlots<N> s = tslots<N>(dyn);
     const InstWs ws = inst_ws(I);
     const uint32_t ps = I.per_step;
     const int64_t k0 = c * I.B;
     const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
     double *F = s.m[0], *L = s.m[1];
-    double *x = s.v[0], *u = s.v[1], *t = s.v[2];
-    for (int j = lane; j < n; j += kW) x[j] = ws.xs[c * n + j];
-    wsync();
+    double *x = s.v[0], *u = s.v[1], *t = s.v[2], *cc = s.v[3];
+    tvec_load<N>(n, ws.xs + c * n, x, lane);
     double fin = 0.0;
+#pragma unroll 1
     for (int64_t k = k0; k < k1; ++k) {
-        if (k == k0 || (ps & kPS_F)) gload(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, ld, lane);
-        if (k == k0 || (ps & kPS_L)) gload(n, m, step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m), m, L, ld, lane);
-        const double* Kk = I.K + k * m * n;
-        for (int a = lane; a < m; a += kW) {
-            double sacc = I.d[k * m + a];
-            for (int j = 0; j < n; ++j) sacc = fma(-Kk[a * n + j], x[j], sacc);
-            u[a] = sacc;
+        const bool first = (k == k0);
+        if (first || (ps & kPS_F)) tload<N>(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, lane);
+        if (first || (ps & kPS_L)) tload<N>(n, m, step_ptr(I.L, ps, kPS_L, k, (int64_t)n * m), m, L, lane);
+        if (first || (ps & kPS_c)) {
+            if (lane < N) cc[lane] = (I.c && lane < n) ? step_ptr(I.c, ps, kPS_c, k, n)[lane] : 0.0;
+            wsync();
+        }
+        if (lane < N) {
+            double a = 0.0;
+            if (lane < m) {
+                const double* Kk = I.K + k * m * n;
+                a = I.d[k * m + lane];
+                for (int j = 0; j < n; ++j) a = fma(-Kk[lane * n + j], x[j], a);
+            }
+            u[lane] = a;
         }
         wsync();
-        if (I.x)
-            for (int j = lane; j < n; j += kW) I.x[k * n + j] = x[j];
-        if (I.u)
-            for (int a = lane; a < m; a += kW) I.u[k * m + a] = u[a];
-        const double* cp = I.c ? step_ptr(I.c, ps, kPS_c, k, n) : nullptr;
-        for (int r = lane; r < n; r += kW) {
-            double a = cp ? cp[r] : 0.0;
-            for (int q = 0; q < n; ++q) a = fma(F[r * ld + q], x[q], a);
-            for (int q = 0; q < m; ++q) a = fma(L[r * ld + q], u[q], a);
-            t[r] = a;
+        if (I.x && lane < n) I.x[k * n + lane] = x[lane];
+        if (I.u && lane < m) I.u[k * m + lane] = u[lane];
+        if (lane < N) {
+            double a = cc[lane];
+#pragma unroll
+            for (int q = 0; q < N; ++q) a = fma(F[lane * ld + q], x[q], a);
+#pragma unroll
+            for (int q = 0; q < N; ++q) a = fma(L[lane * ld + q], u[q], a);
+            t[lane] = a;
         }
         wsync();
-        for (int j = lane; j < n; j += kW) {
-            x[j] = t[j];
-            fin += t[j];
+        if (lane < N) {
+            x[lane] = t[lane];
+            fin += t[lane];
         }
         wsync();
     }
-    if (k1 == I.T && I.x)
-        for (int j = lane; j < n; j += kW) I.x[I.T * n + j] = x[j];
+    if (k1 == I.T && I.x && lane < n) I.x[I.T * n + lane] = x[lane];
     if (__any(!isfinite(fin)) && lane == 0) raise(I.status, 4);
 }
 
@@ -809,39 +1024,83 @@ struct WStage {
 
 size_t wave_lds_bytes(int nmax) { return (size_t)wave_lds(nmax).doubles() * sizeof(double); }
 
-hipError_t wave_solve(const GInst* d_inst, int ninst, int64_t nchunks, int nmax, bool want_fwd, hipStream_t s,
-                      const StageHook* h) {
-    const size_t lds = wave_lds_bytes(nmax);
+int tile_class(int need) {
+    if (need <= 8) return 8;
+    if (need <= 16) return 16;
+    if (need <= 32) return 32;
+    return 0;
+}
+
+size_t tile_lds_bytes(int N) {
+    switch (N) {
+        case 8: return TSlots<8>::doubles() * sizeof(double);
+        case 16: return TSlots<16>::doubles() * sizeof(double);
+        case 32: return TSlots<32>::doubles() * sizeof(double);
+    }
+    return 0;
+}
+
+template <int N>
+struct TileNames;
+template <>
+struct TileNames<8> {
+    static constexpr const char* n[6] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll"};
+};
+template <>
+struct TileNames<16> {
+    static constexpr const char* n[6] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll"};
+};
+template <>
+struct TileNames<32> {
+    static constexpr const char* n[6] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll"};
+};
+
+template <int N>
+static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
+                     const StageHook* h) {
+    const char* const* nm = TileNames<N>::n;
+    const size_t lds = tile_lds_bytes(N);
+    const size_t glds = wave_lds_bytes(N);
     static bool attr = false;
     if (!attr) {
-        const void* ks[] = {(const void*)g_prep, (const void*)g_fold, (const void*)g_chain,
-                            (const void*)g_final, (const void*)g_fchain, (const void*)g_roll};
+        const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N>,
+                            (const void*)t_roll<N>, (const void*)g_prep, (const void*)g_fchain};
         for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
     {
-        WStage st(h, "g_prep", s);
-        g_prep<<<ninst, kW, lds, s>>>(d_inst, ninst, nmax);
+        WStage st(h, nm[0], s);
+        g_prep<<<ninst, kW, glds, s>>>(d_inst, ninst, N);
     }
     {
-        WStage st(h, "g_fold", s);
-        g_fold<<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, nmax);
+        WStage st(h, nm[1], s);
+        t_fold<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
     {
-        WStage st(h, "g_chain", s);
-        g_chain<<<ninst, kW, lds, s>>>(d_inst, ninst, nmax);
+        WStage st(h, nm[2], s);
+        t_chain<N><<<ninst, kW, lds, s>>>(d_inst, ninst);
     }
     {
-        WStage st(h, "g_final", s);
-        g_final<<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, nmax);
+        WStage st(h, nm[3], s);
+        t_final<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
     if (want_fwd) {
         {
-            WStage st(h, "g_fchain", s);
-            g_fchain<<<ninst, kW, lds, s>>>(d_inst, ninst, nmax);
+            WStage st(h, nm[4], s);
+            g_fchain<<<ninst, kW, glds, s>>>(d_inst, ninst, N);
         }
-        WStage st(h, "g_roll", s);
-        g_roll<<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, nmax);
+        WStage st(h, nm[5], s);
+        t_roll<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+    }
+}
+
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
+                      const StageHook* h) {
+    switch (N) {
+        case 8: run_tile<8>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 16: run_tile<16>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 32: run_tile<32>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
