@@ -1,17 +1,20 @@
 """Throughput benchmark of the HIP LQT solver on one MI355X.
 
-Workload (default): one long tracking instance, n = 4 states, m = 2 controls,
-T = 1,000,000 steps, FP64 (the sinusoid-reference generator with
+Headline workload (``value``): one long tracking instance, n = 4 states,
+m = 2 controls, T = 1,000,000 steps, FP64 (sinusoid-reference generator:
 F = I + 0.1 G rescaled to spectral radius 0.99, X = 10 I, U = 0.1 I,
 X_T = 10 I).  One "step" of this benchmark is one full solve: element build,
 reverse scan, gain extraction, forward trajectory scan; every output family
 (S, v, K, d, x, u) is written to device memory.  Inputs are resident in HBM
-before the timed region.
+before the timed region.  ``value`` = time steps solved per second
+(T x solves / elapsed) over the timed region, in which only the dominant
+kernel is bracketed by HIP events (its average duration gives ``roofline``).
 
-Prints one JSON line.  ``value`` = time steps solved per second (T x solves /
-elapsed).  ``roofline`` describes the kernel with the largest device time,
-measured with HIP events recorded around every kernel launch in the timed
-region.  ``cpu_baseline`` times the FP64 CPU oracle on the host.
+Secondary results in the same JSON line (``--workload all``, the default):
+the same instance with float results (MIXED), the uneven batch of 4096
+instances (MIXED), and the serving run with Poisson arrivals (p50/p99
+latency, served steps/s).  ``cpu_baseline`` times the FP64 CPU oracle on
+the host.
 """
 from __future__ import annotations
 
@@ -30,18 +33,19 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 
 
-def algorithmic_bytes_per_step(n, m, p):
-    """Bytes a step must move by the path's contract: reference r_k read once;
-    S_k, v_k, K_k, d_k, x_k, u_k written once (FP64)."""
-    return 8 * (p + n * n + n + m * n + m + n + m)
+def algorithmic_bytes_per_step(n, m, p, osz=8):
+    """Bytes a step must move by the path's contract: reference r_k read once
+    (FP64); S_k, v_k, K_k, d_k, x_k, u_k written once (osz bytes each: 8 for
+    FP64 results, 4 for MIXED)."""
+    return 8 * p + osz * (n * n + n + m * n + m + n + m)
 
 
-def stage_bytes_per_step(stage, n, m, p):
+def stage_bytes_per_step(stage, n, m, p, osz=8):
     """Algorithmic bytes of one kernel's own contract, per step."""
     if stage == "bwd_final":   # reads r_k, writes S_k, v_k, K_k, d_k
-        return 8 * (p + n * n + n + m * n + m)
-    if stage == "fwd_final":   # writes x_k, u_k
-        return 8 * (n + m)
+        return 8 * p + osz * (n * n + n + m * n + m)
+    if stage == "fwd_final":   # reads K_k, d_k, writes x_k, u_k
+        return osz * (m * n + m + n + m)
     if stage in ("bwd_reduce", "prep_varying"):   # reads r_k
         return 8 * p
     return 0
@@ -57,7 +61,87 @@ def path_flops_per_step(n, m):
     return 2 * comb + extract + 2 * aff
 
 
-def run_batched(args, api, inputs, torch):
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu):
+    """One instance n=4, m=2, T=args.T.  Returns the result dict."""
+    n, m, T = 4, 2, args.T
+    prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
+    osz = 8 if prec == "fp64" else 4
+    plan = api.Plan(n, m, prec=prec, device=0, max_steps=T)
+    dp = api.DeviceProblem(prob)
+    do = api.DeviceOutputs(n, m, T, dtype=torch.float64 if osz == 8 else torch.float32)
+    stream = torch.cuda.current_stream(0)
+    for _ in range(warmup):
+        plan.solve([dp], [do], stream)
+    torch.cuda.synchronize()
+    status = int(do.status.item())
+    rel_err = None
+    if not args.no_parity:
+        import oracle
+
+        ref = oracle.solve(prob)
+        got = do.host()
+        rel_err = {f: rel(got[f], ref[f]) for f in api.FAMILIES}
+
+    # Pass 1 (short): every kernel bracketed by events, to find the dominant one.
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(max(3, steps // 10)):
+        plan.solve([dp], [do], stream)
+    stages_all = plan.profile_read()
+    dom_name = max(stages_all.items(), key=lambda kv: kv[1][1] / max(kv[1][0], 1))[0]
+
+    # Timed region: K solves; only the dominant kernel is bracketed by events.
+    plan.profile_select(dom_name)
+    plan.profile_read()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve([dp], [do], stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    dom_launches, dom_ms = plan.profile_read()[dom_name]
+    plan.profile(False)
+    plan.profile_select(None)
+    plan.close()
+
+    ms_per_step = ms_total / steps
+    value = T * steps / (ms_total / 1e3)
+    dom_avg_s = dom_ms / dom_launches / 1e3
+    dom_bytes = stage_bytes_per_step(dom_name, n, m, prob.p, osz) * T
+    achieved = dom_bytes / dom_avg_s / 1e9
+    roofline = {"kernel": dom_name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_us": round(dom_avg_s * 1e6, 2), "launches": dom_launches,
+                "algorithmic_bytes_per_launch": dom_bytes}
+    bytes_step = algorithmic_bytes_per_step(n, m, prob.p, osz)
+    flops_step = path_flops_per_step(n, m)
+    t_bound = max(bytes_step * T / (HBM_PEAK_GBS * 1e9), flops_step * T / (FP64_PEAK_TFLOPS * 1e12))
+    path = {"t_bound_us": round(t_bound * 1e6, 2), "t_measured_us": round(ms_per_step * 1e3, 2),
+            "frac": round(t_bound / (ms_per_step / 1e3), 4), "bytes_per_step": bytes_step,
+            "flops_per_step": round(flops_step, 1)}
+    cpu = None
+    if with_cpu:
+        import oracle
+
+        sps, secs, reps = oracle.time_solve([prob], min_seconds=args.cpu_seconds)
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full sequential FP64 solve(s) of the same T={T} instance ({secs:.1f} s)"}
+    return {"value": value, "ms_per_step": ms_per_step, "status": status, "rel_err": rel_err,
+            "stages_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages_all.items()},
+            "roofline": roofline, "path_roofline": path, "cpu_baseline": cpu, "wall_s": wall}
+
+
+def run_batched(args, api, inputs, torch, prec):
     """Uneven batch: 4096 instances, T log-uniform on [256, 16384], n in
     {4, 8, 16}, m = n / 2, diagonal costs, random-walk references; one
     lqt_solve call per step (all instances, every output family)."""
@@ -65,11 +149,12 @@ def run_batched(args, api, inputs, torch):
     shapes = inputs.batched_shapes(count)
     probs = [inputs.diag_problem(n, n // 2, T, 2, i) for i, (n, T) in enumerate(shapes)]
     steps_total = sum(p.T for p in probs)
-    plan = api.Plan(16, 8, prec="fp64", device=0)
+    plan = api.Plan(16, 8, prec=prec, device=0)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
     dps = [api.DeviceProblem(p) for p in probs]
-    dos = [api.DeviceOutputs(p.n, p.m, p.T) for p in probs]
+    dos = [api.DeviceOutputs(p.n, p.m, p.T, dtype=dtype) for p in probs]
     stream = torch.cuda.current_stream(0)
-    for _ in range(args.warmup):
+    for _ in range(args.batched_warmup):
         plan.solve(dps, dos, stream)
     torch.cuda.synchronize()
     status_bad = sum(int(o.status.item()) != 0 for o in dos)
@@ -82,31 +167,160 @@ def run_batched(args, api, inputs, torch):
             ref = oracle.solve(probs[i])
             got = dos[i].host()
             for f in api.FAMILIES:
-                worst[f] = max(worst[f], float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])))
+                worst[f] = max(worst[f], rel(got[f], ref[f]))
         rel_err = worst
     plan.profile(True)
     plan.profile_read()
+    plan.solve(dps, dos, stream)
+    stages = plan.profile_read()
+    plan.profile(False)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(args.batched_steps):
         plan.solve(dps, dos, stream)
     e1.record(stream)
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batched_steps
+    plan.close()
+    return {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, m = n/2, T log-uniform "
+                        f"[256, 16384], {prec}",
+            "steps_per_solve": steps_total, "ms_per_solve": round(ms, 3),
+            "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s", "status_failures": status_bad,
+            "rel_err_sampled": rel_err,
+            "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+
+
+def dense_flops_per_step(n, m):
+    """Algorithmic flops per step of the dense path (as path_flops_per_step)."""
+    return path_flops_per_step(n, m)
+
+
+def run_dense(args, api, inputs, torch, prec):
+    """Dense batch: 64 instances, n = 64, m = 32, T = 8192, dense SPD costs
+    (Q = W W^T + 0.1 I), spectral radius 0.98, random-walk references."""
+    probs = [inputs.dense_problem(64, 32, args.dense_T, instance=i) for i in range(args.dense_count)]
+    steps_total = sum(p.T for p in probs)
+    plan = api.Plan(64, 32, prec=prec, device=0)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [api.DeviceOutputs(p.n, p.m, p.T, dtype=dtype) for p in probs]
+    stream = torch.cuda.current_stream(0)
+    plan.solve(dps, dos, stream)
+    torch.cuda.synchronize()
+    status_bad = sum(int(o.status.item()) != 0 for o in dos)
+    rel_err = None
+    if not args.no_parity:
+        import oracle
+
+        ref = oracle.solve(probs[0])
+        got = dos[0].host()
+        rel_err = {f: rel(got[f], ref[f]) for f in api.FAMILIES}
+    plan.profile(True)
+    plan.profile_read()
+    plan.solve(dps, dos, stream)
     stages = plan.profile_read()
     plan.profile(False)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(args.batched_steps):
         plan.solve(dps, dos, stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    out = {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, FP64", "steps_per_solve": steps_total,
-           "ms_per_solve": round(ms, 3), "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s",
-           "status_failures": status_bad, "rel_err_sampled": rel_err,
-           "stages_ms_per_solve": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages.items()}}
+    ms = e0.elapsed_time(e1) / args.batched_steps
     plan.close()
-    return out
+    flops = dense_flops_per_step(64, 32) * steps_total
+    tfs = flops / (ms / 1e3) / 1e12
+    return {"workload": f"dense batch {args.dense_count} x (n=64, m=32, T={args.dense_T}), {prec}",
+            "steps_per_solve": steps_total, "ms_per_solve": round(ms, 3),
+            "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s", "status_failures": status_bad,
+            "rel_err_instance0": rel_err, "algorithmic_tflops": round(tfs, 3),
+            "mfma_fp64_peak_frac": round(tfs / FP64_PEAK_TFLOPS, 4),
+            "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+
+
+def run_serving(args, api, inputs, torch, prec):
+    """Poisson arrivals (args.rate req/s for args.serve_seconds s), nx ~ U{4..32},
+    nu = ceil(nx / 2), T log-uniform on [64, 65536], diagonal costs and
+    random-walk references; each request asks for K, d, x, u.  The first
+    args.pool requests of the stream are generated and kept on the device;
+    request i replays entry i % pool (its shape is that entry's)."""
+    reqs = inputs.serving_requests(args.rate, args.serve_seconds)
+    P = min(args.pool, len(reqs))
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    want = ("K", "d", "x", "u")
+    ent = []
+    for j in range(P):
+        _, n, m, T = reqs[j]
+        p = inputs.diag_problem(n, m, T, 4, j)
+        ent.append((p, api.DeviceProblem(p), api.DeviceOutputs(n, m, T, dtype=dtype, want=want, status=False)))
+    torch.cuda.synchronize()
+    plan = api.Plan(32, 16, prec=prec, device=0, hbm_budget_bytes=args.serve_pool_gb << 30)
+    # warm-up: the first requests of the pool, once
+    tick = [plan.submit(ent[j][1], ent[j][2]) for j in range(min(P, 16))]
+    for t in tick:
+        while plan.poll(t) is None:
+            pass
+    N = len(reqs)
+    busy = [False] * P
+    inflight = {}
+    lat = []
+    served_steps = 0
+    waits = 0
+    i = 0
+    t0 = time.perf_counter()
+    last_done = 0.0
+    next_note = 5.0
+    while i < N or inflight:
+        now = time.perf_counter() - t0
+        if now > next_note:
+            print(f"[serving] t={now:.1f}s submitted={i}/{N} in_flight={len(inflight)}", file=sys.stderr, flush=True)
+            next_note += 5.0
+        while i < N and reqs[i][0] <= now:
+            e = i % P
+            if busy[e]:
+                waits += 1
+                break
+            tk = plan.submit(ent[e][1], ent[e][2])
+            inflight[tk] = (reqs[i][0], e)
+            busy[e] = True
+            i += 1
+        for tk in list(inflight):
+            st = plan.poll(tk)
+            if st is not None:
+                t_done = time.perf_counter() - t0
+                arr, e = inflight.pop(tk)
+                if st != 0:
+                    raise RuntimeError(f"served request failed with status {st}")
+                lat.append(t_done - arr)
+                served_steps += ent[e][0].T
+                busy[e] = False
+                last_done = t_done
+    stats = plan.serve_stats()
+    plan.close()
+    lat_ms = np.array(lat) * 1e3
+    offered = sum(r[3] for r in reqs) / args.serve_seconds
+    rel_err = None
+    if not args.no_parity:
+        import oracle
+
+        # the four cheapest entries (oracle cost ~ n^3 T) against the oracle
+        order = sorted(range(P), key=lambda j: ent[j][0].n ** 3 * ent[j][0].T)[:4]
+        worst = {f: 0.0 for f in want}
+        for j in order:
+            ref = oracle.solve(ent[j][0])
+            got = ent[j][2].host()
+            for f in want:
+                worst[f] = max(worst[f], rel(got[f], ref[f]))
+        rel_err = worst
+    return {"workload": f"serving: Poisson {args.rate:g} req/s for {args.serve_seconds:g} s, nx ~ U{{4..32}}, "
+                        f"nu = ceil(nx/2), T log-uniform [64, 65536], {prec}, outputs K d x u",
+            "requests": len(lat), "distinct_requests_on_device": P,
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "max_ms": round(float(lat_ms.max()), 3), "served_steps_per_s": round(served_steps / last_done, 1),
+            "offered_steps_per_s": round(offered, 1), "elapsed_s": round(last_done, 3),
+            "submit_waits_on_busy_entry": waits, "serve_stats": stats, "rel_err_sampled": rel_err}
 
 
 def main():
@@ -118,8 +332,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batched"), default="single")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving"), default="all")
+    ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
+                    help="precision of a --workload single/batched/serving run")
     ap.add_argument("--count", type=int, default=4096)
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--batched-warmup", type=int, default=1)
+    ap.add_argument("--dense-count", type=int, default=64)
+    ap.add_argument("--dense-T", type=int, default=8192)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--pool", type=int, default=512)
+    ap.add_argument("--serve-pool-gb", type=int, default=16)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -132,108 +356,44 @@ def main():
     from paper_2104_03186_amd import api, inputs
 
     if args.workload == "batched":
-        print(json.dumps(run_batched(args, api, inputs, torch)), flush=True)
+        print(json.dumps(run_batched(args, api, inputs, torch, args.prec or "mixed")), flush=True)
         return
-
-    n, m, T = 4, 2, args.T
-    prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
-    dev = "cuda:0"
-    plan = api.Plan(n, m, prec="fp64", device=0, max_steps=T)
-    dp = api.DeviceProblem(prob, dev)
-    do = api.DeviceOutputs(n, m, T, dev)
-    stream = torch.cuda.current_stream(0)
-
-    for _ in range(args.warmup):
-        plan.solve([dp], [do], stream)
-    torch.cuda.synchronize()
-    status = int(do.status.item())
-
-    rel_err = None
-    if not args.no_parity:
-        import oracle
-
-        ref = oracle.solve(prob)
-        got = do.host()
-        rel_err = {f: float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in api.FAMILIES}
-
-    # Timed region: K solves, every kernel bracketed by HIP events on `stream`.
-    plan.profile(True)
-    plan.profile_read()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.solve([dp], [do], stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    stages = plan.profile_read()
-    plan.profile(False)
-
-    # Same loop without per-kernel events, for reference.
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.solve([dp], [do], stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_total_plain = e0.elapsed_time(e1)
-
-    ms_per_step = ms_total / args.steps
-    value = T * args.steps / (ms_total / 1e3)
-
-    dom = max(stages.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_launches, dom_ms) = dom
-    dom_avg_s = dom_ms / dom_launches / 1e3
-    dom_bytes = stage_bytes_per_step(dom_name, n, m, prob.p) * T
-    achieved = dom_bytes / dom_avg_s / 1e9
-    roofline = {"kernel": dom_name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_us": round(dom_avg_s * 1e6, 2), "algorithmic_bytes_per_launch": dom_bytes}
-
-    bytes_step = algorithmic_bytes_per_step(n, m, prob.p)
-    flops_step = path_flops_per_step(n, m)
-    t_bound = max(bytes_step * T / (HBM_PEAK_GBS * 1e9), flops_step * T / (FP64_PEAK_TFLOPS * 1e12))
-    path = {"t_bound_us": round(t_bound * 1e6, 2), "t_measured_us": round(ms_per_step * 1e3, 2),
-            "frac": round(t_bound / (ms_per_step / 1e3), 4), "bytes_per_step": bytes_step,
-            "flops_per_step": round(flops_step, 1)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        sps, secs, reps = oracle.time_solve([prob], min_seconds=args.cpu_seconds)
-        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full sequential FP64 solve(s) of the same T={T} instance ({secs:.1f} s)"}
-
+    if args.workload == "dense":
+        print(json.dumps(run_dense(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        return
+    prec = args.prec or "fp64"
+    main_res = run_single(args, api, inputs, torch, prec, args.steps, args.warmup, not args.no_cpu_baseline)
     out = {
-        "metric": "LQT time-steps solved/s (single long instance, FP64 parallel scan)",
-        "value": round(value, 1),
+        "metric": "LQT time-steps solved/s (single long instance, parallel scan)",
+        "value": round(main_res["value"], 1),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "ms_per_step_no_events": round(ms_total_plain / args.steps, 4),
+        "ms_per_step": round(main_res["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded sinusoid-reference tracking generator)",
-        "config": {"workload": f"single LQT instance nx=4 nu=2 T={T} FP64", "nx": n, "nu": m, "T": T,
-                   "precision": "fp64"},
-        "status": status,
-        "rel_err": rel_err,
-        "stages_ms_per_solve": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages.items()},
-        "roofline": roofline,
-        "path_roofline": path,
-        "cpu_baseline": cpu,
-        "wall_s": round(wall, 3),
+        "dtype": "f64" if prec == "fp64" else "f64 arithmetic, f32 results",
+        "data": "synthetic (seeded generators: sinusoid-reference tracking; diagonal-cost random-walk batches)",
+        "config": {"workload": f"single LQT instance nx=4 nu=2 T={args.T} {prec}", "nx": 4, "nu": 2, "T": args.T,
+                   "precision": prec},
+        "status": main_res["status"],
+        "rel_err": main_res["rel_err"],
+        "stages_avg_ms": main_res["stages_avg_ms"],
+        "roofline": main_res["roofline"],
+        "path_roofline": main_res["path_roofline"],
+        "cpu_baseline": main_res["cpu_baseline"],
     }
-    plan.close()
+    if args.workload == "all":
+        mixed = run_single(args, api, inputs, torch, "mixed", args.steps, args.warmup, False)
+        out["single_mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "status", "rel_err", "roofline")}
+        out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
+        out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
+        out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")
     print(json.dumps(out), flush=True)
 
 

@@ -37,7 +37,8 @@
  * lqt_last_error returns a human-readable description of the last synchronous
  * error of a plan.
  *
- * Thread safety: a plan may be used by one host thread at a time.
+ * Thread safety: the calls on one plan are serialised by a lock inside the
+ * plan, so a plan may be shared by host threads.
  */
 #ifndef LQT_H
 #define LQT_H
@@ -63,8 +64,15 @@ typedef enum {
 
 typedef enum {
     LQT_PREC_FP64 = 0,   /* all arithmetic and all outputs in IEEE double          */
-    LQT_PREC_MIXED = 1   /* outputs in float; precision-sensitive chains in double */
+    LQT_PREC_MIXED = 1   /* outputs in float; the scan arithmetic stays in double  */
 } lqt_precision;
+/* LQT_PREC_MIXED: every combination, solve and product of the scan is carried
+ * in double and only the stored results are rounded to float (relative error
+ * of order 1e-7 per result family against the double solution).  The vector
+ * units issue non-packed float and double instructions at the same rate, so
+ * float arithmetic would buy no speed on these paths and would cost accuracy
+ * in the C and b chains of the combination rule (Section IV-A); the float
+ * results halve the output traffic, which bounds the small-n pipeline. */
 
 /* Bits of lqt_problem.per_step: a set bit means the matrix has a leading time
  * axis of length T (one matrix per step k = 0..T-1); a clear bit means one
@@ -130,16 +138,43 @@ lqt_status lqt_plan(const lqt_plan_desc *desc, lqt_plan_t *out);
 lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
                      int32_t count, void *stream);
 
-/* Serving interface: admit one instance for asynchronous solution on the
- * plan's internal stream.  Returns LQT_EBUSY when the queue is full and
- * LQT_ENOMEM when the request can never fit the memory budget.  *ticket
- * identifies the request for lqt_poll. */
+/* Serving interface (continuous batching).  lqt_submit queues one instance
+ * and returns at once with *ticket.  Queued requests are launched in FIFO
+ * order as batches: whenever one of the plan's serving streams is idle, the
+ * longest prefix of the queue whose workspace fits one free range of the
+ * plan's serving pool (hbm_budget_bytes, or 8 GiB when that is 0) becomes one
+ * batch on that stream.  Several batches run on the device at once; a
+ * request that arrives while others are running joins the next batch as soon
+ * as a stream and pool memory are free.  Batching never changes a result:
+ * every instance is solved exactly as by lqt_solve alone.  Progress is made
+ * inside lqt_submit and lqt_poll.
+ *   LQT_ENOMEM: the request alone needs more than the serving pool.
+ *   LQT_EBUSY:  max_inflight requests are already queued or running.
+ * The caller's input and output buffers must stay valid until lqt_poll has
+ * returned something other than LQT_EAGAIN for the ticket. */
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem *prob, const lqt_outputs *out,
                       uint64_t *ticket);
 
-/* LQT_EAGAIN while the request is in flight; afterwards the instance's
- * status (LQT_OK on success).  A ticket may be polled to completion once. */
+/* LQT_EAGAIN while the request is queued or running; afterwards the
+ * instance's status (LQT_OK on success).  A ticket may be polled to
+ * completion once. */
 lqt_status lqt_poll(lqt_plan_t plan, uint64_t ticket);
+
+/* Counters of the serving interface since the plan was created. */
+typedef struct {
+    int64_t submitted;        /* requests accepted by lqt_submit                    */
+    int64_t completed;        /* requests whose batch has finished                  */
+    int64_t batches;          /* batches launched                                   */
+    int32_t queued;           /* requests waiting for a stream or pool memory       */
+    int32_t running_batches;  /* batches on the device now                          */
+    int32_t max_running_batches; /* most batches ever on the device at once         */
+    int32_t max_batch;        /* largest batch launched (requests)                  */
+    size_t pool_bytes;        /* size of the serving pool                           */
+    size_t pool_in_use;       /* bytes held by running batches                      */
+    size_t pool_peak;         /* most bytes ever held at once                       */
+} lqt_serve_stats;
+
+lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats *out);
 
 /* Wait for all work of the plan, then release it and its workspace. */
 lqt_status lqt_destroy(lqt_plan_t plan);
@@ -154,6 +189,10 @@ typedef struct {
 } lqt_stage_time;
 
 lqt_status lqt_profile_enable(lqt_plan_t plan, int32_t enable);
+
+/* Restrict the timing to the launches of one stage (NULL: every stage), so
+ * that only that kernel is bracketed by events. */
+lqt_status lqt_profile_select(lqt_plan_t plan, const char *stage);
 
 /* Waits for the recorded events, writes up to `max` per-stage totals (in
  * first-launch order) into out, clears the accumulators and returns the

@@ -19,8 +19,8 @@ STATUS_NAMES = {OK: "LQT_OK", EINVAL: "LQT_EINVAL", ENOMEM: "LQT_ENOMEM", ENOTPD
 PREC_FP64, PREC_MIXED = 0, 1
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
-EXPORTED = ("lqt_plan", "lqt_solve", "lqt_submit", "lqt_poll", "lqt_destroy", "lqt_profile_enable",
-            "lqt_profile_read", "lqt_last_error")
+EXPORTED = ("lqt_plan", "lqt_solve", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
+            "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error")
 
 _vp = ctypes.c_void_p
 
@@ -44,6 +44,13 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_nx", ctypes.c_int32), ("max_nu", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t), ("max_steps", ctypes.c_int64),
                 ("max_inflight", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("running_batches", ctypes.c_int32),
+                ("max_running_batches", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_size_t), ("pool_in_use", ctypes.c_size_t), ("pool_peak", ctypes.c_size_t)]
 
 
 _lib = None
@@ -72,10 +79,14 @@ def load() -> ctypes.CDLL:
     lib.lqt_submit.restype = ctypes.c_int
     lib.lqt_poll.argtypes = [_vp, ctypes.c_uint64]
     lib.lqt_poll.restype = ctypes.c_int
+    lib.lqt_serve_stats_read.argtypes = [_vp, ctypes.POINTER(ServeStats)]
+    lib.lqt_serve_stats_read.restype = ctypes.c_int
     lib.lqt_destroy.argtypes = [_vp]
     lib.lqt_destroy.restype = ctypes.c_int
     lib.lqt_profile_enable.argtypes = [_vp, ctypes.c_int32]
     lib.lqt_profile_enable.restype = ctypes.c_int
+    lib.lqt_profile_select.argtypes = [_vp, ctypes.c_char_p]
+    lib.lqt_profile_select.restype = ctypes.c_int
     lib.lqt_profile_read.argtypes = [_vp, ctypes.POINTER(StageTime), ctypes.c_int32]
     lib.lqt_profile_read.restype = ctypes.c_int32
     lib.lqt_last_error.argtypes = [_vp]

@@ -88,6 +88,8 @@ class Plan:
         current stream).  Asynchronous."""
         if len(probs) != len(outs):
             raise ValueError("probs and outs differ in length")
+        for o in outs:
+            self._check_dtype(o)
         n = len(probs)
         P = (_lib.Problem * max(n, 1))(*[p.struct() for p in probs])
         O = (_lib.Outputs * max(n, 1))(*[o.struct() for o in outs])
@@ -96,7 +98,14 @@ class Plan:
         sp = ctypes.c_void_p(stream.cuda_stream)
         _lib.check(_lib.load().lqt_solve(self._h, P, O, n, sp), self._h)
 
+    def _check_dtype(self, out: DeviceOutputs) -> None:
+        want = torch.float64 if self.prec == "fp64" else torch.float32
+        for k, t in out.t.items():
+            if t is not None and t.dtype != want:
+                raise TypeError(f"output {k} is {t.dtype}; a {self.prec} plan writes {want}")
+
     def submit(self, prob: DeviceProblem, out: DeviceOutputs) -> int:
+        self._check_dtype(out)
         t = ctypes.c_uint64()
         ps, os_ = prob.struct(), out.struct()
         _lib.check(_lib.load().lqt_submit(self._h, ctypes.byref(ps), ctypes.byref(os_), ctypes.byref(t)), self._h)
@@ -111,9 +120,19 @@ class Plan:
             raise _lib.LQTError(rc, _lib.last_error(self._h))
         return rc
 
+    def serve_stats(self) -> Dict[str, int]:
+        """Counters of the serving interface (lqt_serve_stats_read)."""
+        st = _lib.ServeStats()
+        _lib.check(_lib.load().lqt_serve_stats_read(self._h, ctypes.byref(st)), self._h)
+        return {f: int(getattr(st, f)) for f, _ in _lib.ServeStats._fields_}
+
     def profile(self, enable: bool = True) -> None:
         """Bracket every kernel launch with HIP events (see profile_read)."""
         _lib.check(_lib.load().lqt_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_select(self, stage: Optional[str] = None) -> None:
+        """Time only the launches of ``stage`` (None: every stage)."""
+        _lib.check(_lib.load().lqt_profile_select(self._h, None if stage is None else stage.encode()), self._h)
 
     def profile_read(self) -> Dict[str, tuple]:
         """{stage: (launches, total_ms)} since the last read (synchronises)."""

@@ -15,9 +15,11 @@ struct SmallArgs {
     int64_t T;
     int32_t n, m, p, pT;
     uint32_t per_step;
-    // outputs (device pointers; S, v, x, u may be null)
-    double *S, *v, *K, *d, *x, *u;
+    // outputs (device pointers; S, v, x, u may be null); element type is
+    // double, or float when f32 is set
+    void *S, *v, *K, *d, *x, *u;
     int32_t* status;
+    int32_t f32;
     // workspace
     double* cst;       // per-instance constants
     double* der;       // per-step derived data (time-varying problems)
@@ -42,7 +44,7 @@ struct StageHook {
 // One instance of the wavefront-per-chunk pipeline (device-resident array).
 struct GInst {
     const double *F, *c, *L, *U, *H, *X, *r, *HT, *XT, *rT, *x0;
-    double *S, *v, *K, *d, *x, *u;
+    void *S, *v, *K, *d, *x, *u;  // element type: double, or float for FP32 results
     int32_t* status;
     int64_t T;
     int32_t n, m, p, pT;
@@ -53,15 +55,17 @@ struct GInst {
     double* ws;       // instance workspace (wave_inst_ws_doubles)
 };
 
-int64_t wave_inst_ws_doubles(int n, int m, int p, int64_t NC);
 size_t wave_lds_bytes(int nmax);
 
 // Size-class variant of the wavefront pipeline: matrices zero-padded to N x N
 // with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
 int tile_class(int need);
 size_t tile_lds_bytes(int N);
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
-                      const StageHook* h);
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
+                      hipStream_t s, const StageHook* h);
+// Workgroup class (N = 64): n, p, pT <= 64, m <= 32, time-invariant except c.
+hipError_t block_solve(const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32, hipStream_t s,
+                       const StageHook* h);
 
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);

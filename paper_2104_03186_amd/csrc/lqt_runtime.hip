@@ -1,14 +1,15 @@
 // Host runtime of the LQT solver: plans, validation, workspace, launches,
-// status and the asynchronous submit/poll interface.  Implements include/lqt.h.
+// status and the continuous-batching serving interface (submit/poll).
+// Implements include/lqt.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstring>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -17,12 +18,20 @@
 
 #include "../../include/lqt.h"
 #include "lqt_internal.hpp"
+#include "lqt_ws.hpp"
 
 namespace {
 
-constexpr int kMaxNx = 32;         // largest state dimension of this build's kernels
-constexpr int kWaveMaxN = 32;      // wavefront path: n, m, p, pT up to this
+constexpr int kMaxNx = 64;         // largest state dimension of this build's kernels
+constexpr int kWaveMaxN = 64;      // chunked paths: n, p, pT up to this (m up to 32 above 32)
 constexpr int64_t kSmallMinT = 8192;  // lane-per-element path for long n <= 4 instances
+
+// Serving defaults: device pool for in-flight requests (when the plan sets no
+// budget), concurrent batches (one stream each), requests per batch, queue.
+constexpr size_t kDefaultServePool = size_t(8) << 30;
+constexpr int kServeSlots = 4;
+constexpr int kServeBatchMax = 512;
+constexpr int kDefaultQueue = 4096;
 
 // Path of an instance: a function of the instance alone (never of the batch),
 // so a result is the same alone and in any mix.  LQT_PATH=small|wave forces
@@ -49,13 +58,6 @@ int wave_chunk(int64_t T) {
 
 thread_local std::string g_create_error;
 
-struct Request {
-    uint64_t ticket;
-    hipEvent_t done;
-    int32_t* status_dev;  // plan-owned per-request status word
-    int32_t* user_status;
-};
-
 }  // namespace
 
 struct Profiler {
@@ -64,6 +66,7 @@ struct Profiler {
         hipEvent_t a, b;
     };
     bool on = false;
+    std::string only;  // record only this stage ("" = every stage)
     std::vector<hipEvent_t> pool;
     std::vector<Rec> pending;
     hipEvent_t cur_a = nullptr;
@@ -83,33 +86,67 @@ struct Profiler {
     }
     static void begin(void* ctx, const char* name, hipStream_t s) {
         Profiler* p = (Profiler*)ctx;
+        p->cur_name = nullptr;
+        if (!p->only.empty() && p->only != name) return;
         p->cur_a = p->get();
         p->cur_name = name;
         (void)hipEventRecord(p->cur_a, s);
     }
     static void end(void* ctx, hipStream_t s) {
         Profiler* p = (Profiler*)ctx;
+        if (!p->cur_name) return;
         hipEvent_t b = p->get();
         (void)hipEventRecord(b, s);
         p->pending.push_back({p->cur_name, p->cur_a, b});
     }
 };
 
-struct lqt_plan_s {
-    lqt_plan_desc desc{};
-    Profiler prof;
+// Device workspace of one stream of launches, plus the pinned host copy of
+// the wavefront-path instance table and the event of its last upload (the
+// host table is rewritten only after that copy has finished).
+struct Arena {
     char* ws = nullptr;
-    size_t ws_cap = 0;
-    std::string err;
-    hipStream_t serve_stream = nullptr;
-    uint64_t next_ticket = 1;
-    std::unordered_map<uint64_t, Request> inflight;
-    std::vector<int32_t*> free_status;
-    // wavefront path: pinned host copy of the instance table and the event of
-    // its last upload (the buffer is reused only after that copy finished)
+    size_t cap = 0;
+    bool owned = true;  // false: ws points into the serving pool
     lqt::GInst* ginst_host = nullptr;
     size_t ginst_cap = 0;
     hipEvent_t ginst_done = nullptr;
+};
+
+// One batch of served requests in flight on its own stream.
+struct Slot {
+    hipStream_t stream = nullptr;
+    Arena arena;
+    int32_t* status_dev = nullptr;   // [kServeBatchMax] per-request status words
+    int32_t* status_host = nullptr;  // pinned copy, valid once `done` has fired
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    size_t off = 0, len = 0;         // range of the serving pool
+    std::vector<uint64_t> tickets;
+};
+
+struct PendingReq {
+    uint64_t ticket;
+    lqt_problem p;
+    lqt_outputs o;
+};
+
+struct lqt_plan_s {
+    lqt_plan_desc desc{};
+    Profiler prof;
+    Arena main;
+    std::string err;
+    std::recursive_mutex mu;
+    // serving state
+    char* pool = nullptr;
+    size_t pool_size = 0;
+    std::map<size_t, size_t> free_ranges;  // offset -> length
+    std::vector<Slot> slots;
+    std::deque<PendingReq> pending;
+    std::unordered_map<uint64_t, int> state;  // ticket -> -1 queued/running, else final status
+    size_t live = 0;                          // queued + running requests
+    uint64_t next_ticket = 1;
+    lqt_serve_stats stats{};
 };
 
 namespace {
@@ -172,6 +209,34 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
     return L;
 }
 
+// Workspace of one wavefront-path instance, and of its K, d scratch when the
+// caller does not take K and d.
+size_t wave_bytes(const lqt_problem& p) {
+    const int B = wave_chunk(p.T);
+    const int64_t NC = (p.T + B - 1) / B;
+    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, p.nyT, NC) * sizeof(double));
+}
+size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
+    return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
+}
+
+// Device bytes of one launch group: the small-path instances run one after
+// another in one region (the largest), each wavefront-path instance has its
+// own region, then the instance table.
+struct BatchSize {
+    size_t small = 0, wave = 0;
+    size_t nwave = 0;
+    void add(const lqt_problem& p, const lqt_outputs& o) {
+        if (path_of(p) == Path::Small) {
+            small = std::max(small, align_up(layout_for(p, !o.K, !o.d).total));
+        } else {
+            wave += wave_bytes(p) + wave_kd_bytes(p, o);
+            ++nwave;
+        }
+    }
+    size_t total() const { return small + (nwave ? wave + align_up(nwave * sizeof(lqt::GInst)) : 0); }
+};
+
 lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, int idx) {
     if (p.nx < 1 || p.nu < 1 || p.ny < 1 || p.nyT < 1)
         return fail(plan, LQT_EINVAL, "instance %d: dimensions must be >= 1 (nx=%d nu=%d ny=%d nyT=%d)", idx,
@@ -180,9 +245,20 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
-    if (path_of(p) == Path::Wave && std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
-        return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
-                    p.nu, p.ny, p.nyT, kWaveMaxN);
+    if (path_of(p) == Path::Wave) {
+        if (std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
+            return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
+                        p.nu, p.ny, p.nyT, kWaveMaxN);
+        if (lqt::block_class(p.nx, p.nu, p.ny, p.nyT)) {
+            if (p.nu > lqt::kBlockM)
+                return fail(plan, LQT_ENOTSUP, "instance %d: nu=%d above %d needs all dimensions <= 32", idx, p.nu,
+                            lqt::kBlockM);
+            if (p.per_step & ~(uint32_t)LQT_PS_c)
+                return fail(plan, LQT_ENOTSUP,
+                            "instance %d: above 32 states only c may vary per step (per_step=0x%x)", idx,
+                            p.per_step);
+        }
+    }
     if (p.per_step & ~63u) return fail(plan, LQT_EINVAL, "instance %d: unknown per_step bits 0x%x", idx, p.per_step);
     if (!p.F || !p.L || !p.H || !p.X || !p.U || !p.r || !p.HT || !p.XT || !p.rT || !p.x0)
         return fail(plan, LQT_EINVAL, "instance %d: a required input pointer is NULL", idx);
@@ -198,55 +274,305 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     return LQT_OK;
 }
 
-lqt_status ensure_ws(lqt_plan_t plan, size_t bytes) {
-    if (bytes <= plan->ws_cap) return LQT_OK;
+// Grow an owned arena to `bytes` (synchronous: the old buffer may be in use).
+lqt_status ensure_ws(lqt_plan_t plan, Arena& A, size_t bytes) {
+    if (bytes <= A.cap) return LQT_OK;
+    if (!A.owned) return fail(plan, LQT_ENOMEM, "batch needs %zu bytes, its pool range holds %zu", bytes, A.cap);
     if (plan->desc.hbm_budget_bytes && bytes > plan->desc.hbm_budget_bytes)
         return fail(plan, LQT_ENOMEM, "workspace of %zu bytes exceeds the plan budget of %zu bytes", bytes,
                     plan->desc.hbm_budget_bytes);
-    if (plan->ws) {
-        if (hipDeviceSynchronize() != hipSuccess || hipFree(plan->ws) != hipSuccess)
+    if (A.ws) {
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(A.ws) != hipSuccess)
             return fail(plan, LQT_EHIP, "hipFree of the old workspace failed");
-        plan->ws = nullptr;
-        plan->ws_cap = 0;
+        A.ws = nullptr;
+        A.cap = 0;
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(plan, LQT_ENOMEM, "hipMalloc of %zu workspace bytes failed", bytes);
     }
-    plan->ws = (char*)p;
-    plan->ws_cap = bytes;
+    A.ws = (char*)p;
+    A.cap = bytes;
     return LQT_OK;
 }
 
-lqt_status launch_one(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, hipStream_t s,
+lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const lqt_outputs& o, hipStream_t s,
                       int32_t* status_override) {
     const bool fwd = o.x || o.u;
     const bool need_K = !o.K, need_d = !o.d;
     Layout L = layout_for(p, need_K, need_d);
-    lqt_status st = ensure_ws(plan, L.total);
-    if (st != LQT_OK) return st;
     lqt::SmallArgs a{};
     a.F = p.F; a.c = p.c; a.L = p.L; a.U = p.U; a.H = p.H; a.X = p.X; a.r = p.r;
     a.HT = p.HT; a.XT = p.XT; a.rT = p.rT; a.x0 = p.x0;
     a.T = p.T; a.n = p.nx; a.m = p.nu; a.p = p.ny; a.pT = p.nyT;
     a.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-    a.S = (double*)o.S; a.v = (double*)o.v;
-    a.K = o.K ? (double*)o.K : (double*)(plan->ws + L.K);
-    a.d = o.d ? (double*)o.d : (double*)(plan->ws + L.d);
-    a.x = (double*)o.x; a.u = (double*)o.u;
+    a.S = o.S; a.v = o.v;
+    a.K = o.K ? o.K : (void*)(base + L.K);
+    a.d = o.d ? o.d : (void*)(base + L.d);
+    a.x = o.x; a.u = o.u;
+    a.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
     a.status = status_override ? status_override : o.status;
-    a.cst = (double*)(plan->ws + L.cst);
-    a.der = (double*)(plan->ws + L.der);
-    a.lane_el = (double*)(plan->ws + L.lane_el);
-    a.wave_val = (double*)(plan->ws + L.wave_val);
-    a.lane_aff = (double*)(plan->ws + L.lane_aff);
-    a.wave_x = (double*)(plan->ws + L.wave_x);
+    a.cst = (double*)(base + L.cst);
+    a.der = (double*)(base + L.der);
+    a.lane_el = (double*)(base + L.lane_el);
+    a.wave_val = (double*)(base + L.wave_val);
+    a.lane_aff = (double*)(base + L.lane_aff);
+    a.wave_x = (double*)(base + L.wave_x);
     a.NC = L.NC; a.B = L.B; a.NG = L.NG;
     a.want_fwd = fwd ? 1 : 0;
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr);
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return LQT_OK;
+}
+
+// Solve a set of instances on stream s in arena A.  status_override (if not
+// null) gives per-instance device status words used instead of outs[i].status.
+lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
+                     hipStream_t s, int32_t* const* status_override) {
+    // partition by path; wavefront instances ordered by size class
+    std::vector<int> small, wave;
+    for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
+    auto cls = [&](int i) {
+        const lqt_problem& p = probs[i];
+        return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
+    };
+    std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
+    // workspace: [small-path region (largest small instance)] [wave region] [instance table]
+    BatchSize bs;
+    for (int i = 0; i < count; ++i) bs.add(probs[i], outs[i]);
+    std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
+    size_t wave_need = 0;
+    for (size_t j = 0; j < wave.size(); ++j) {
+        ws_off[j] = (int64_t)wave_need;
+        wave_need += wave_bytes(probs[wave[j]]);
+        kd_off[j] = (int64_t)wave_need;
+        wave_need += wave_kd_bytes(probs[wave[j]], outs[wave[j]]);
+    }
+    lqt_status st = ensure_ws(plan, A, bs.total());
+    if (st != LQT_OK) return st;
+    for (int i : small) {
+        st = launch_one(plan, A.ws, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
+        if (st != LQT_OK) return st;
+    }
+    if (wave.empty()) return LQT_OK;
+    if (A.ginst_cap < wave.size()) {
+        if (A.ginst_done) (void)hipEventSynchronize(A.ginst_done);
+        if (A.ginst_host) (void)hipHostFree(A.ginst_host);
+        A.ginst_host = nullptr;
+        A.ginst_cap = 0;
+        const size_t cap = std::max<size_t>(wave.size(), 64);
+        if (hipHostMalloc((void**)&A.ginst_host, cap * sizeof(lqt::GInst), 0) != hipSuccess)
+            return fail(plan, LQT_ENOMEM, "pinned instance table allocation failed");
+        A.ginst_cap = cap;
+    } else if (A.ginst_done) {
+        (void)hipEventSynchronize(A.ginst_done);  // previous upload has left the buffer
+    }
+    char* wbase = A.ws + bs.small;
+    std::vector<char> want_fwd_c(wave.size(), 0);
+    int64_t chunk0 = 0;
+    for (size_t j = 0; j < wave.size(); ++j) {
+        if (j > 0 && cls(wave[j]) != cls(wave[j - 1])) chunk0 = 0;  // each class numbers its own chunks
+        const lqt_problem& p = probs[wave[j]];
+        const lqt_outputs& o = outs[wave[j]];
+        lqt::GInst& g = A.ginst_host[j];
+        g = lqt::GInst{};
+        g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
+        g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
+        g.S = o.S; g.v = o.v; g.x = o.x; g.u = o.u;
+        double* kd = (double*)(wbase + kd_off[j]);  // sized for FP64 gains; FP32 ones use part of it
+        g.K = o.K ? o.K : (void*)kd;
+        g.d = o.d ? o.d : (void*)(kd + (size_t)p.T * p.nu * p.nx);
+        g.status = status_override ? status_override[wave[j]] : o.status;
+        g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
+        g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+        g.B = wave_chunk(p.T);
+        g.NC = (p.T + g.B - 1) / g.B;
+        g.chunk0 = chunk0;
+        chunk0 += g.NC;
+        g.ws = (double*)(wbase + ws_off[j]);
+        want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
+    }
+    lqt::GInst* d_inst = (lqt::GInst*)(wbase + bs.wave);
+    if (hipMemcpyAsync(d_inst, A.ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return fail(plan, LQT_EHIP, "instance table upload failed");
+    if (!A.ginst_done && hipEventCreateWithFlags(&A.ginst_done, hipEventDisableTiming) != hipSuccess)
+        return fail(plan, LQT_EHIP, "event creation failed");
+    (void)hipEventRecord(A.ginst_done, s);
+    lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
+    for (size_t j0 = 0; j0 < wave.size();) {
+        size_t j1 = j0;
+        int64_t nch = 0;
+        bool fwd = false;
+        while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
+            nch += A.ginst_host[j1].NC;
+            fwd = fwd || want_fwd_c[j1];
+            ++j1;
+        }
+        hipError_t e = lqt::tile_solve(cls(wave[j0]), d_inst + j0, (int)(j1 - j0), nch, fwd,
+                                       plan->desc.prec == LQT_PREC_MIXED, s, plan->prof.on ? &hook : nullptr);
+        if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
+        j0 = j1;
+    }
+    return LQT_OK;
+}
+
+void arena_release(Arena& A) {
+    if (A.ginst_done) (void)hipEventDestroy(A.ginst_done);
+    if (A.ginst_host) (void)hipHostFree(A.ginst_host);
+    if (A.owned && A.ws) (void)hipFree(A.ws);
+    A = Arena{};
+}
+
+// ---- serving: continuous batching -----------------------------------------
+//
+// Requests wait in a FIFO.  Whenever a slot (stream) is idle, the longest
+// prefix of the queue whose workspace fits one free range of the device pool
+// is launched on it as one batch.  Up to kServeSlots batches run at once on
+// the device; a finished batch returns its range and slot, and the next batch
+// takes whatever has arrived in the meantime.
+
+size_t serve_bytes(const lqt_problem& p, const lqt_outputs& o) {
+    BatchSize b;
+    b.add(p, o);
+    return b.total();
+}
+
+bool pool_take(lqt_plan_t plan, size_t len, size_t& off) {
+    for (auto it = plan->free_ranges.begin(); it != plan->free_ranges.end(); ++it) {
+        if (it->second >= len) {
+            off = it->first;
+            const size_t rest = it->second - len;
+            plan->free_ranges.erase(it);
+            if (rest) plan->free_ranges[off + len] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+size_t pool_largest(lqt_plan_t plan) {
+    size_t b = 0;
+    for (auto& kv : plan->free_ranges) b = std::max(b, kv.second);
+    return b;
+}
+
+void pool_give(lqt_plan_t plan, size_t off, size_t len) {
+    auto it = plan->free_ranges.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != plan->free_ranges.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        plan->free_ranges.erase(nx);
+    }
+    if (it != plan->free_ranges.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            plan->free_ranges.erase(it);
+        }
+    }
+}
+
+lqt_status serve_init(lqt_plan_t plan) {
+    if (plan->pool) return LQT_OK;
+    const size_t want = plan->desc.hbm_budget_bytes ? plan->desc.hbm_budget_bytes : kDefaultServePool;
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(plan, LQT_ENOMEM, "hipMalloc of the %zu-byte serving pool failed", want);
+    }
+    plan->pool = (char*)p;
+    plan->pool_size = want;
+    plan->free_ranges.clear();
+    plan->free_ranges[0] = want;
+    plan->stats.pool_bytes = want;
+    plan->slots.resize(kServeSlots);
+    for (Slot& s : plan->slots) {
+        s.arena.owned = false;
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc(&s.status_dev, kServeBatchMax * sizeof(int32_t)) != hipSuccess ||
+            hipHostMalloc((void**)&s.status_host, kServeBatchMax * sizeof(int32_t), 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(plan, LQT_EHIP, "serving slot set-up failed");
+        }
+    }
+    return LQT_OK;
+}
+
+// Retire finished batches, then launch queued requests on idle slots.
+lqt_status serve_pump(lqt_plan_t plan) {
+    for (Slot& s : plan->slots) {
+        if (!s.busy) continue;
+        hipError_t q = hipEventQuery(s.done);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (q != hipSuccess) return fail(plan, LQT_EHIP, "serving batch failed: %s", hipGetErrorString(q));
+        for (size_t i = 0; i < s.tickets.size(); ++i) plan->state[s.tickets[i]] = s.status_host[i];
+        plan->live -= s.tickets.size();
+        plan->stats.completed += (int64_t)s.tickets.size();
+        plan->stats.running_batches -= 1;
+        plan->stats.pool_in_use -= s.len;
+        s.tickets.clear();
+        pool_give(plan, s.off, s.len);
+        s.busy = false;
+    }
+    for (Slot& s : plan->slots) {
+        if (plan->pending.empty()) break;
+        if (s.busy) continue;
+        const size_t room = pool_largest(plan);
+        BatchSize bs;
+        size_t take = 0;
+        while (take < plan->pending.size() && take < (size_t)kServeBatchMax) {
+            BatchSize t = bs;
+            t.add(plan->pending[take].p, plan->pending[take].o);
+            if (t.total() > room) break;
+            bs = t;
+            ++take;
+        }
+        if (take == 0) break;  // the head waits for memory (FIFO: nothing overtakes it)
+        size_t off = 0;
+        (void)pool_take(plan, bs.total(), off);
+        std::vector<lqt_problem> ps(take);
+        std::vector<lqt_outputs> os(take);
+        std::vector<int32_t*> ovr(take);
+        for (size_t i = 0; i < take; ++i) {
+            ps[i] = plan->pending[i].p;
+            os[i] = plan->pending[i].o;
+            ovr[i] = s.status_dev + i;
+            s.tickets.push_back(plan->pending[i].ticket);
+        }
+        plan->pending.erase(plan->pending.begin(), plan->pending.begin() + take);
+        s.arena.ws = plan->pool + off;
+        s.arena.cap = bs.total();
+        s.off = off;
+        s.len = bs.total();
+        s.busy = true;
+        lqt_serve_stats& S = plan->stats;
+        S.batches += 1;
+        S.running_batches += 1;
+        S.max_running_batches = std::max(S.max_running_batches, S.running_batches);
+        S.max_batch = std::max(S.max_batch, (int32_t)take);
+        S.pool_in_use += s.len;
+        S.pool_peak = std::max(S.pool_peak, S.pool_in_use);
+        lqt_status st = solve_all(plan, s.arena, ps.data(), os.data(), (int32_t)take, s.stream, ovr.data());
+        if (st == LQT_OK &&
+            hipMemcpyAsync(s.status_host, s.status_dev, take * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream) !=
+                hipSuccess)
+            st = fail(plan, LQT_EHIP, "status copy failed");
+        for (size_t i = 0; st == LQT_OK && i < take; ++i)
+            if (os[i].status &&
+                hipMemcpyAsync(os[i].status, s.status_dev + i, sizeof(int32_t), hipMemcpyDefault, s.stream) !=
+                    hipSuccess)
+                st = fail(plan, LQT_EHIP, "status copy failed");
+        if (st == LQT_OK && hipEventRecord(s.done, s.stream) != hipSuccess)
+            st = fail(plan, LQT_EHIP, "event record failed");
+        if (st != LQT_OK) return st;
+    }
     return LQT_OK;
 }
 
@@ -261,8 +587,8 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
         return fail(nullptr, LQT_EINVAL, "lqt_plan: max_nx and max_nu must be >= 1");
     if (desc->max_nx > kMaxNx)
         return fail(nullptr, LQT_ENOTSUP, "lqt_plan: max_nx=%d exceeds this build's limit %d", desc->max_nx, kMaxNx);
-    if (desc->prec != LQT_PREC_FP64)
-        return fail(nullptr, LQT_ENOTSUP, "lqt_plan: precision %d is not provided by this build", (int)desc->prec);
+    if (desc->prec != LQT_PREC_FP64 && desc->prec != LQT_PREC_MIXED)
+        return fail(nullptr, LQT_EINVAL, "lqt_plan: unknown precision %d", (int)desc->prec);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -274,7 +600,7 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     lqt_plan_s* p = new (std::nothrow) lqt_plan_s();
     if (!p) return fail(nullptr, LQT_ENOMEM, "lqt_plan: out of host memory");
     p->desc = *desc;
-    if (p->desc.max_inflight <= 0) p->desc.max_inflight = 64;
+    if (p->desc.max_inflight <= 0) p->desc.max_inflight = kDefaultQueue;
     if (desc->max_steps > 0) {
         lqt_problem probe{};
         probe.nx = desc->max_nx; probe.nu = desc->max_nu; probe.ny = desc->max_nx; probe.nyT = desc->max_nx;
@@ -291,11 +617,11 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
         {
             const int64_t B = wave_chunk(desc->max_steps);
             const int64_t NC = (desc->max_steps + B - 1) / B;
-            const size_t w = (size_t)lqt::wave_inst_ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, NC) * 8 +
+            const size_t w = (size_t)lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, desc->max_nx, NC) * 8 +
                              (size_t)desc->max_steps * (desc->max_nu * desc->max_nx + desc->max_nu) * 8 + 4096;
             need = std::max(need, w);
         }
-        lqt_status st = ensure_ws(p, need);
+        lqt_status st = ensure_ws(p, p->main, need);
         if (st != LQT_OK) {
             g_create_error = p->err;
             delete p;
@@ -306,118 +632,10 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     return LQT_OK;
 }
 
-}  // extern "C"
-
-namespace {
-
-// Solve a set of instances on stream s.  status_override (if not null) gives
-// a per-instance device status word used instead of outs[i].status.
-lqt_status solve_all(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
-                     hipStream_t s, int32_t* const* status_override) {
-    // partition by path; wavefront instances ordered by size class
-    std::vector<int> small, wave;
-    for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
-    auto cls = [&](int i) {
-        const lqt_problem& p = probs[i];
-        return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
-    };
-    std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
-    // workspace: [small-path region (largest small instance)] [wave region]
-    size_t small_need = 0;
-    for (int i : small) small_need = std::max(small_need, layout_for(probs[i], !outs[i].K, !outs[i].d).total);
-    small_need = align_up(small_need);
-    size_t wave_need = 0;
-    std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
-    for (size_t j = 0; j < wave.size(); ++j) {
-        const lqt_problem& p = probs[wave[j]];
-        const int B = wave_chunk(p.T);
-        const int64_t NC = (p.T + B - 1) / B;
-        ws_off[j] = (int64_t)wave_need;
-        wave_need = align_up(wave_need + (size_t)lqt::wave_inst_ws_doubles(p.nx, p.nu, p.ny, NC) * sizeof(double));
-        kd_off[j] = (int64_t)wave_need;
-        const lqt_outputs& o = outs[wave[j]];
-        if (!o.K || !o.d)
-            wave_need = align_up(wave_need + (size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double));
-    }
-    const size_t inst_bytes = align_up(wave.size() * sizeof(lqt::GInst));
-    const size_t total = small_need + (wave.empty() ? 0 : wave_need + inst_bytes);
-    lqt_status st = ensure_ws(plan, total);
-    if (st != LQT_OK) return st;
-    for (int i : small) {
-        st = launch_one(plan, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
-        if (st != LQT_OK) return st;
-    }
-    if (wave.empty()) return LQT_OK;
-    if (plan->ginst_cap < wave.size()) {
-        if (plan->ginst_done) (void)hipEventSynchronize(plan->ginst_done);
-        if (plan->ginst_host) (void)hipHostFree(plan->ginst_host);
-        plan->ginst_host = nullptr;
-        plan->ginst_cap = 0;
-        if (hipHostMalloc((void**)&plan->ginst_host, wave.size() * sizeof(lqt::GInst), 0) != hipSuccess)
-            return fail(plan, LQT_ENOMEM, "pinned instance table allocation failed");
-        plan->ginst_cap = wave.size();
-    } else if (plan->ginst_done) {
-        (void)hipEventSynchronize(plan->ginst_done);  // previous upload has left the buffer
-    }
-    char* wbase = plan->ws + small_need;
-    std::vector<char> want_fwd_c(wave.size(), 0);
-    int64_t chunk0 = 0;
-    for (size_t j = 0; j < wave.size(); ++j) {
-        if (j > 0 && cls(wave[j]) != cls(wave[j - 1])) chunk0 = 0;  // each class numbers its own chunks
-        const lqt_problem& p = probs[wave[j]];
-        const lqt_outputs& o = outs[wave[j]];
-        lqt::GInst& g = plan->ginst_host[j];
-        g = lqt::GInst{};
-        g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
-        g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
-        g.S = (double*)o.S; g.v = (double*)o.v; g.x = (double*)o.x; g.u = (double*)o.u;
-        double* kd = (double*)(wbase + kd_off[j]);
-        g.K = o.K ? (double*)o.K : kd;
-        g.d = o.d ? (double*)o.d : kd + (size_t)p.T * p.nu * p.nx;
-        g.status = status_override ? status_override[wave[j]] : o.status;
-        g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
-        g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-        g.B = wave_chunk(p.T);
-        g.NC = (p.T + g.B - 1) / g.B;
-        g.chunk0 = chunk0;
-        chunk0 += g.NC;
-        g.ws = (double*)(wbase + ws_off[j]);
-        // forward pass only if some instance of the launch wants it; instances
-        // without x and u still get their (cheap) roll-out into K/d-free paths
-        want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
-    }
-    lqt::GInst* d_inst = (lqt::GInst*)(wbase + wave_need);
-    if (hipMemcpyAsync(d_inst, plan->ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return fail(plan, LQT_EHIP, "instance table upload failed");
-    if (!plan->ginst_done && hipEventCreateWithFlags(&plan->ginst_done, hipEventDisableTiming) != hipSuccess)
-        return fail(plan, LQT_EHIP, "event creation failed");
-    (void)hipEventRecord(plan->ginst_done, s);
-    lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
-    for (size_t j0 = 0; j0 < wave.size();) {
-        size_t j1 = j0;
-        int64_t nch = 0;
-        bool fwd = false;
-        while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
-            nch += plan->ginst_host[j1].NC;
-            fwd = fwd || want_fwd_c[j1];
-            ++j1;
-        }
-        hipError_t e = lqt::tile_solve(cls(wave[j0]), d_inst + j0, (int)(j1 - j0), nch, fwd, s,
-                                       plan->prof.on ? &hook : nullptr);
-        if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
-        j0 = j1;
-    }
-    return LQT_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
 lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
                      void* stream) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_solve: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
     plan->err.clear();
     if (count < 0 || (count > 0 && (!probs || !outs))) return fail(plan, LQT_EINVAL, "lqt_solve: bad count/arrays");
     for (int i = 0; i < count; ++i) {
@@ -426,90 +644,81 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
     }
     if (count == 0) return LQT_OK;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-    return solve_all(plan, probs, outs, count, (hipStream_t)stream, nullptr);
+    return solve_all(plan, plan->main, probs, outs, count, (hipStream_t)stream, nullptr);
 }
 
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, uint64_t* ticket) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_submit: NULL plan");
     if (!prob || !out || !ticket) return fail(plan, LQT_EINVAL, "lqt_submit: NULL argument");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
     plan->err.clear();
     lqt_status st = validate(plan, *prob, *out, 0);
     if (st != LQT_OK) return st;
-    if ((int)plan->inflight.size() >= plan->desc.max_inflight)
-        return fail(plan, LQT_EBUSY, "lqt_submit: %zu requests in flight (max %d)", plan->inflight.size(),
-                    plan->desc.max_inflight);
-    Layout L = layout_for(*prob, !out->K, !out->d);
-    if (plan->desc.hbm_budget_bytes && L.total > plan->desc.hbm_budget_bytes)
-        return fail(plan, LQT_ENOMEM, "lqt_submit: request needs %zu bytes, budget %zu", L.total,
-                    plan->desc.hbm_budget_bytes);
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-    if (!plan->serve_stream && hipStreamCreateWithFlags(&plan->serve_stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(plan, LQT_EHIP, "hipStreamCreate failed");
-    Request r{};
-    if (!plan->free_status.empty()) {
-        r.status_dev = plan->free_status.back();
-        plan->free_status.pop_back();
-    } else if (hipMalloc(&r.status_dev, sizeof(int32_t)) != hipSuccess) {
-        return fail(plan, LQT_ENOMEM, "lqt_submit: status allocation failed");
-    }
-    int32_t* ovr[1] = {r.status_dev};
-    st = solve_all(plan, prob, out, 1, plan->serve_stream, ovr);
-    if (st == LQT_OK && out->status)
-        if (hipMemcpyAsync(out->status, r.status_dev, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                           plan->serve_stream) != hipSuccess)
-            st = fail(plan, LQT_EHIP, "status copy failed");
-    if (st == LQT_OK && (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess ||
-                         hipEventRecord(r.done, plan->serve_stream) != hipSuccess))
-        st = fail(plan, LQT_EHIP, "event record failed");
-    if (st != LQT_OK) {
-        plan->free_status.push_back(r.status_dev);
-        return st;
-    }
-    r.ticket = plan->next_ticket++;
-    r.user_status = out->status;
-    plan->inflight[r.ticket] = r;
+    st = serve_init(plan);
+    if (st != LQT_OK) return st;
+    const size_t need = serve_bytes(*prob, *out);
+    if (need > plan->pool_size)
+        return fail(plan, LQT_ENOMEM, "lqt_submit: request needs %zu device bytes, the serving pool holds %zu", need,
+                    plan->pool_size);
+    st = serve_pump(plan);  // retire finished work first: it frees queue places
+    if (st != LQT_OK) return st;
+    if (plan->live >= (size_t)plan->desc.max_inflight)
+        return fail(plan, LQT_EBUSY, "lqt_submit: %zu requests queued or running (max %d)", plan->live,
+                    plan->desc.max_inflight);
+    PendingReq r{plan->next_ticket++, *prob, *out};
+    plan->pending.push_back(r);
+    plan->state[r.ticket] = -1;
+    ++plan->live;
+    plan->stats.submitted += 1;
     *ticket = r.ticket;
-    return LQT_OK;
+    return serve_pump(plan);
 }
 
 lqt_status lqt_poll(lqt_plan_t plan, uint64_t ticket) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_poll: NULL plan");
-    auto it = plan->inflight.find(ticket);
-    if (it == plan->inflight.end()) return fail(plan, LQT_EINVAL, "lqt_poll: unknown ticket %llu",
-                                                (unsigned long long)ticket);
-    hipError_t q = hipEventQuery(it->second.done);
-    if (q == hipErrorNotReady) {
-        (void)hipGetLastError();
-        return LQT_EAGAIN;
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    auto it = plan->state.find(ticket);
+    if (it == plan->state.end())
+        return fail(plan, LQT_EINVAL, "lqt_poll: unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second < 0) {
+        if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+        lqt_status st = serve_pump(plan);
+        if (st != LQT_OK) return st;
+        it = plan->state.find(ticket);
+        if (it->second < 0) return LQT_EAGAIN;
     }
-    if (q != hipSuccess) return fail(plan, LQT_EHIP, "lqt_poll: event query failed");
-    int32_t code = 0;
-    if (hipMemcpy(&code, it->second.status_dev, sizeof code, hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(plan, LQT_EHIP, "lqt_poll: status read failed");
-    (void)hipEventDestroy(it->second.done);
-    plan->free_status.push_back(it->second.status_dev);
-    plan->inflight.erase(it);
+    const int code = it->second;
+    plan->state.erase(it);
     return (lqt_status)code;
+}
+
+lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats* out) {
+    if (!plan || !out) return fail(plan, LQT_EINVAL, "lqt_serve_stats_read: NULL argument");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    *out = plan->stats;
+    out->queued = (int32_t)plan->pending.size();
+    return LQT_OK;
 }
 
 lqt_status lqt_destroy(lqt_plan_t plan) {
     if (!plan) return LQT_OK;
     (void)hipSetDevice(plan->desc.device);
     (void)hipDeviceSynchronize();
-    for (auto& kv : plan->inflight) {
-        (void)hipEventDestroy(kv.second.done);
-        (void)hipFree(kv.second.status_dev);
+    for (Slot& s : plan->slots) {
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.status_dev) (void)hipFree(s.status_dev);
+        if (s.status_host) (void)hipHostFree(s.status_host);
+        arena_release(s.arena);
     }
-    for (int32_t* s : plan->free_status) (void)hipFree(s);
-    if (plan->serve_stream) (void)hipStreamDestroy(plan->serve_stream);
+    if (plan->pool) (void)hipFree(plan->pool);
     for (auto& r : plan->prof.pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
-    if (plan->ginst_done) (void)hipEventDestroy(plan->ginst_done);
-    if (plan->ginst_host) (void)hipHostFree(plan->ginst_host);
-    if (plan->ws) (void)hipFree(plan->ws);
+    arena_release(plan->main);
     delete plan;
     return LQT_OK;
 }
@@ -520,8 +729,16 @@ lqt_status lqt_profile_enable(lqt_plan_t plan, int32_t enable) {
     return LQT_OK;
 }
 
+lqt_status lqt_profile_select(lqt_plan_t plan, const char* stage) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_profile_select: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->prof.only = stage ? stage : "";
+    return LQT_OK;
+}
+
 int32_t lqt_profile_read(lqt_plan_t plan, lqt_stage_time* out, int32_t max) {
     if (!plan) return -(int32_t)fail(nullptr, LQT_EINVAL, "lqt_profile_read: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
     Profiler& P = plan->prof;
     for (auto& r : P.pending) {
         if (hipEventSynchronize(r.b) != hipSuccess) return -(int32_t)fail(plan, LQT_EHIP, "event sync failed");

@@ -255,118 +255,88 @@ LQT_DI void load_step(const SmallArgs& a, int64_t k, Step<N, M>& st) {
 
 // ---- coalesced transfers -----------------------------------------------------
 //
-// Output rows of one time step k are R contiguous doubles (S_k, K_k, ...).  In
-// the chunked layout lane l of a wavefront handles row (cw0 + l) * B + j at
-// step j, so lanes are B rows apart.  Per-lane stores would issue one small
-// request per lane and per double; instead each lane deposits its row in LDS
-// (row stride R | 1 doubles, conflict-free) and the wavefront writes the 64
-// rows with 16-byte pieces, consecutive lanes on consecutive pieces.
+// Output rows of one time step k are R contiguous elements (S_k, K_k, ...) of
+// the result type OT (double, or float for FP32 results).  In the chunked
+// layout lane l of a wavefront handles row (cw0 + l) * B + j at step j, so
+// lanes are B rows apart.  Per-lane stores would issue one small request per
+// lane and per element; instead each lane deposits its row in LDS (row stride
+// R | 1 elements, conflict-free) and the wavefront writes the 64 rows in
+// vector pieces, consecutive lanes on consecutive pieces.
+
+// Elements per vector piece for rows of R elements of type OT: 16 bytes where
+// R allows it, else 8, else one element (rows start 16-byte aligned when the
+// array does and R * sizeof(OT) is a multiple of 16).
+template <typename OT, int R>
+struct PieceW {
+    static constexpr int v16 = 16 / (int)sizeof(OT);
+    static constexpr int W = (R % v16 == 0) ? v16 : ((sizeof(OT) == 4 && R % 2 == 0) ? 2 : 1);
+};
+
+template <typename OT, int W>
+struct VecOf {
+    typedef OT T __attribute__((ext_vector_type(W)));
+};
+
+// W elements from src (any type) to g, converted to OT, as one access
+template <int W, typename OT, typename ST>
+LQT_DI void put_piece(OT* g, const ST* src) {
+    if constexpr (W == 1) {
+        g[0] = (OT)src[0];
+    } else {
+        typename VecOf<OT, W>::T t;
+        LQT_UNROLL for (int i = 0; i < W; ++i) t[i] = (OT)src[i];
+        *reinterpret_cast<typename VecOf<OT, W>::T*>(g) = t;
+    }
+}
+
+template <int W, typename OT, typename DT>
+LQT_DI void get_piece(const OT* g, DT* dst) {
+    if constexpr (W == 1) {
+        dst[0] = (DT)g[0];
+    } else {
+        const typename VecOf<OT, W>::T t = *reinterpret_cast<const typename VecOf<OT, W>::T*>(g);
+        LQT_UNROLL for (int i = 0; i < W; ++i) dst[i] = (DT)t[i];
+    }
+}
 
 template <int R>
 struct Staged {
     static constexpr int stride = R | 1;
-    static constexpr int doubles = kWave * stride;
+    static constexpr int elems = kWave * stride;
 };
 
-template <int R>
-LQT_DI void lds_put_row(double* lds, int lane, const double* v) {
-    LQT_UNROLL for (int i = 0; i < R; ++i) lds[lane * Staged<R>::stride + i] = v[i];
-}
-
-template <int R>
-LQT_DI void lds_get_row(const double* lds, int lane, double* v) {
-    LQT_UNROLL for (int i = 0; i < R; ++i) v[i] = lds[lane * Staged<R>::stride + i];
+template <int R, typename OT>
+LQT_DI void lds_put_row(OT* lds, int lane, const double* v) {
+    LQT_UNROLL for (int i = 0; i < R; ++i) lds[lane * Staged<R>::stride + i] = (OT)v[i];
 }
 
 // rows (cw0 + rec) * B + j, valid when cw0 + rec < NC and the row < T
-template <int R>
-LQT_DI void wave_store_rows(const double* lds, double* g, int64_t cw0, int64_t NC, int B, int j, int64_t T,
-                            int lane) {
+template <int R, typename OT>
+LQT_DI void wave_store_rows(const OT* lds, OT* g, int64_t cw0, int64_t NC, int B, int j, int64_t T, int lane) {
     constexpr int st = Staged<R>::stride;
-    if constexpr (R % 2 == 0) {
-        constexpr int P = R / 2;
-        LQT_UNROLL for (int it = 0; it < P; ++it) {
-            const int piece = it * kWave + lane;
-            const int rec = piece / P;
-            const int off = (piece - rec * P) * 2;
-            const int64_t c = cw0 + rec;
-            const int64_t row = c * B + j;
-            if (c < NC && row < T) {
-                double2 v;
-                v.x = lds[rec * st + off];
-                v.y = lds[rec * st + off + 1];
-                *reinterpret_cast<double2*>(g + row * R + off) = v;
-            }
-        }
-    } else {
-        LQT_UNROLL for (int it = 0; it < R; ++it) {
-            const int piece = it * kWave + lane;
-            const int rec = piece / R;
-            const int off = piece - rec * R;
-            const int64_t c = cw0 + rec;
-            const int64_t row = c * B + j;
-            if (c < NC && row < T) g[row * R + off] = lds[rec * st + off];
-        }
+    constexpr int W = PieceW<OT, R>::W;
+    constexpr int P = R / W;  // pieces per row
+    LQT_UNROLL for (int it = 0; it < P; ++it) {
+        const int piece = it * kWave + lane;
+        const int rec = piece / P;
+        const int off = (piece - rec * P) * W;
+        const int64_t c = cw0 + rec;
+        const int64_t row = c * B + j;
+        if (c < NC && row < T) put_piece<W>(g + row * R + off, lds + rec * st + off);
     }
 }
 
-template <int R>
-LQT_DI void wave_load_rows(double* lds, const double* g, int64_t cw0, int64_t NC, int B, int j, int64_t T,
-                           int lane) {
-    constexpr int st = Staged<R>::stride;
-    if constexpr (R % 2 == 0) {
-        constexpr int P = R / 2;
-        LQT_UNROLL for (int it = 0; it < P; ++it) {
-            const int piece = it * kWave + lane;
-            const int rec = piece / P;
-            const int off = (piece - rec * P) * 2;
-            const int64_t c = cw0 + rec;
-            const int64_t row = c * B + j;
-            if (c < NC && row < T) {
-                const double2 v = *reinterpret_cast<const double2*>(g + row * R + off);
-                lds[rec * st + off] = v.x;
-                lds[rec * st + off + 1] = v.y;
-            }
-        }
-    } else {
-        LQT_UNROLL for (int it = 0; it < R; ++it) {
-            const int piece = it * kWave + lane;
-            const int rec = piece / R;
-            const int off = piece - rec * R;
-            const int64_t c = cw0 + rec;
-            const int64_t row = c * B + j;
-            if (c < NC && row < T) lds[rec * st + off] = g[row * R + off];
-        }
-    }
+// Direct per-lane row store/load (vector pieces where the row length allows).
+template <int R, typename OT>
+LQT_DI void store_row(OT* g, const double* v) {
+    constexpr int W = PieceW<OT, R>::W;
+    LQT_UNROLL for (int i = 0; i < R; i += W) put_piece<W>(g + i, v + i);
 }
 
-// Direct per-lane row store/load with 16-byte pieces when R is even (rows of
-// an even number of doubles keep 16-byte alignment).
-template <int R>
-LQT_DI void store_row(double* g, const double* v) {
-    if constexpr (R % 2 == 0) {
-        LQT_UNROLL for (int i = 0; i < R; i += 2) {
-            double2 t;
-            t.x = v[i];
-            t.y = v[i + 1];
-            *reinterpret_cast<double2*>(g + i) = t;
-        }
-    } else {
-        LQT_UNROLL for (int i = 0; i < R; ++i) g[i] = v[i];
-    }
-}
-
-template <int R>
-LQT_DI void load_row(const double* g, double* v) {
-    if constexpr (R % 2 == 0) {
-        LQT_UNROLL for (int i = 0; i < R; i += 2) {
-            const double2 t = *reinterpret_cast<const double2*>(g + i);
-            v[i] = t.x;
-            v[i + 1] = t.y;
-        }
-    } else {
-        LQT_UNROLL for (int i = 0; i < R; ++i) v[i] = g[i];
-    }
+template <int R, typename OT>
+LQT_DI void load_row(const OT* g, double* v) {
+    constexpr int W = PieceW<OT, R>::W;
+    LQT_UNROLL for (int i = 0; i < R; i += W) get_piece<W>(g + i, v + i);
 }
 
 template <int N>
@@ -529,13 +499,17 @@ LQT_DI void load_inv_shared(const SmallArgs& a, InvShared<N, M>& sh) {
     if (t < N * N) sh.W[t] = (a.p == N) ? a.cst[CL::W + t] : 0.0;
 }
 
-template <int N, int M, int MODE, bool ALL>
+template <int N, int M, int MODE, bool ALL, typename OT>
 __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
     using S = Sym<N>;
     using CL = CstLayout<N, M>;
     constexpr int VS = S::size + N;
-    __shared__ __align__(16) double shS[kBlock / kWave][Staged<N * N>::doubles];
-    __shared__ __align__(16) double shK[kBlock / kWave][Staged<M * N>::doubles];
+    __shared__ __align__(16) OT shS[kBlock / kWave][Staged<N * N>::elems];
+    __shared__ __align__(16) OT shK[kBlock / kWave][Staged<M * N>::elems];
+    OT* const oS = (OT*)a.S;
+    OT* const oV = (OT*)a.v;
+    OT* const oK = (OT*)a.K;
+    OT* const oD = (OT*)a.d;
     __shared__ InvShared<N, M> inv;
     if constexpr (MODE != kVar) {
         load_inv_shared<N, M>(a, inv);
@@ -549,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
     const bool active = c < a.NC;
     const int B = a.B;
     const int64_t T = a.T;
-    const bool wantS = ALL || a.S, wantV = ALL || a.v;
+    const bool wantS = ALL || oS, wantV = ALL || oV;
     Aff<N> phi;
     aff_identity<N>(phi);
     double Sv[S::size], v[N];
@@ -569,8 +543,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
         if (k1 == T) {  // terminal value S_T, v_T
             double full[N * N];
             full_from_packed<N>(Sv, full);
-            if (wantS) store_row<N * N>(a.S + T * N * N, full);
-            if (wantV) store_row<N>(a.v + T * N, v);
+            if (wantS) store_row<N * N>(oS + T * N * N, full);
+            if (wantV) store_row<N>(oV + T * N, v);
         }
     }
     const uint32_t ps = a.per_step;
@@ -619,8 +593,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
                 lds_put_row<N * N>(shS[wv], lane, full);
             }
             lds_put_row<M * N>(shK[wv], lane, K);
-            if (wantV) store_row<N>(a.v + k * N, v);
-            store_row<M>(a.d + k * M, d);
+            if (wantV) store_row<N>(oV + k * N, v);
+            store_row<M>(oD + k * M, d);
             // compose the chunk map: phi <- phi o (Ft, ct)
             Aff<N> step;
             LQT_UNROLL for (int i = 0; i < N * N; ++i) step.F[i] = Ft[i];
@@ -628,8 +602,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
             aff_after<N>(step, phi);
         }
         wave_sync();
-        if (wantS) wave_store_rows<N * N>(shS[wv], a.S, cw0, a.NC, B, j, T, lane);
-        wave_store_rows<M * N>(shK[wv], a.K, cw0, a.NC, B, j, T, lane);
+        if (wantS) wave_store_rows<N * N>(shS[wv], oS, cw0, a.NC, B, j, T, lane);
+        wave_store_rows<M * N>(shK[wv], oK, cw0, a.NC, B, j, T, lane);
         wave_sync();
     };
     // Reference rows (fast mode): step j uses rA when B-1-j is even, rB
@@ -663,10 +637,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
 
 // Forward roll-out with a compile-time chunk length: every gain row of the
 // chunk is loaded into registers before the first store.
-template <int N, int M, int BC>
+template <int N, int M, int BC, typename OT>
 __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.NC) return;
+    const OT* const iK = (const OT*)a.K;
+    const OT* const iD = (const OT*)a.d;
+    OT* const oX = (OT*)a.x;
+    OT* const oU = (OT*)a.u;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t T = a.T;
     const int64_t k0 = c * BC;
@@ -675,8 +653,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
     double gk[BC][KD];
     LQT_UNROLL for (int j = 0; j < BC; ++j) {
         const int64_t kk = clamp_row(k0 + j, k0, k1, true);
-        load_row<M * N>(a.K + kk * M * N, gk[j]);
-        load_row<M>(a.d + kk * M, gk[j] + M * N);
+        load_row<M * N>(iK + kk * M * N, gk[j]);
+        load_row<M>(iD + kk * M, gk[j] + M * N);
     }
     double F[N * N], L[N * M], cc[N];
     LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = a.F[i];
@@ -707,15 +685,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
             t[i] = s;
         }
         if (k < k1) {
-            store_row<N>(a.x + k * N, x);
-            store_row<M>(a.u + k * M, u);
+            store_row<N>(oX + k * N, x);
+            store_row<M>(oU + k * M, u);
             LQT_UNROLL for (int i = 0; i < N; ++i) {
                 x[i] = t[i];
                 fin += t[i];
             }
         }
     }
-    if (k1 == T) store_row<N>(a.x + T * N, x);
+    if (k1 == T) store_row<N>(oX + T * N, x);
     if (!isfinite(fin)) raise_status(a.status, 4);
 }
 
@@ -772,21 +750,25 @@ __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
     }
 }
 
-template <int N, int M, int MODE, bool ALL>
+template <int N, int M, int MODE, bool ALL, typename OT>
 __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.NC) return;
+    const OT* const iK = (const OT*)a.K;
+    const OT* const iD = (const OT*)a.d;
+    OT* const oX = (OT*)a.x;
+    OT* const oU = (OT*)a.u;
     const int lane = threadIdx.x & (kWave - 1);
     const int B = a.B;
     const int64_t T = a.T;
     const int64_t k0 = c * B;
     const int64_t k1 = (k0 + B < T) ? k0 + B : T;
-    const bool wantX = ALL || a.x, wantU = ALL || a.u;
+    const bool wantX = ALL || oX, wantU = ALL || oU;
     constexpr int KD = M * N + M;  // one gain row: K_k then d_k
     auto load_gain = [&](int64_t k, double* gk) {
         const int64_t kk = clamp_row(k, k0, k1, true);
-        load_row<M * N>(a.K + kk * M * N, gk);
-        load_row<M>(a.d + kk * M, gk + M * N);
+        load_row<M * N>(iK + kk * M * N, gk);
+        load_row<M>(iD + kk * M, gk + M * N);
     };
     const uint32_t ps = a.per_step;
     // time-invariant F, L, c stay in registers for the whole chunk
@@ -829,8 +811,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
             LQT_UNROLL for (int i = 0; i < N; ++i) s = fma(-gk[q * N + i], x[i], s);
             u[q] = s;
         }
-        if (wantX) store_row<N>(a.x + k * N, x);
-        if (wantU) store_row<M>(a.u + k * M, u);
+        if (wantX) store_row<N>(oX + k * N, x);
+        if (wantU) store_row<M>(oU + k * M, u);
         LQT_UNROLL for (int i = 0; i < N; ++i) {
             double s = cc[i];
             LQT_UNROLL for (int q = 0; q < N; ++q) s = fma(F[i * N + q], x[q], s);
@@ -848,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
         if (k + 1 < k1) step(k + 1, gB);
         load_gain(k + 3, gB);
     }
-    if (k1 == T && wantX) store_row<N>(a.x + T * N, x);
+    if (k1 == T && wantX) store_row<N>(oX + T * N, x);
     if (!isfinite(fin)) raise_status(a.status, 4);
 }
 
@@ -865,7 +847,7 @@ struct Stage {
     }
 };
 
-template <int N, int M, int MODE>
+template <int N, int M, int MODE, typename OT>
 static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     using CL = CstLayout<N, M>;
     const unsigned grid = (unsigned)((a.NC + kBlock - 1) / kBlock);
@@ -893,8 +875,8 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     }
     {
         Stage st(h, "bwd_final", s);
-        if (all) k_bwd_final<N, M, MODE, true><<<grid, kBlock, 0, s>>>(a);
-        else k_bwd_final<N, M, MODE, false><<<grid, kBlock, 0, s>>>(a);
+        if (all) k_bwd_final<N, M, MODE, true, OT><<<grid, kBlock, 0, s>>>(a);
+        else k_bwd_final<N, M, MODE, false, OT><<<grid, kBlock, 0, s>>>(a);
     }
     if (a.want_fwd) {
         {
@@ -906,23 +888,29 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         bool fdone = false;
         if constexpr (N % 2 == 0 && M % 2 == 0) {
             fdone = true;
-            if (regs && a.B == 4) k_fwd_final_regs<N, M, 4><<<grid, kBlock, 0, s>>>(a);
-            else if (regs && a.B == 8) k_fwd_final_regs<N, M, 8><<<grid, kBlock, 0, s>>>(a);
-            else if (regs && a.B == 16) k_fwd_final_regs<N, M, 16><<<grid, kBlock, 0, s>>>(a);
+            if (regs && a.B == 4) k_fwd_final_regs<N, M, 4, OT><<<grid, kBlock, 0, s>>>(a);
+            else if (regs && a.B == 8) k_fwd_final_regs<N, M, 8, OT><<<grid, kBlock, 0, s>>>(a);
+            else if (regs && a.B == 16) k_fwd_final_regs<N, M, 16, OT><<<grid, kBlock, 0, s>>>(a);
             else fdone = false;
         }
         if (fdone) {
-        } else if (all) k_fwd_final<N, M, MODE, true><<<grid, kBlock, 0, s>>>(a);
-        else k_fwd_final<N, M, MODE, false><<<grid, kBlock, 0, s>>>(a);
+        } else if (all) k_fwd_final<N, M, MODE, true, OT><<<grid, kBlock, 0, s>>>(a);
+        else k_fwd_final<N, M, MODE, false, OT><<<grid, kBlock, 0, s>>>(a);
     }
+}
+
+template <int N, int M, typename OT>
+static void run_typed(const SmallArgs& a, hipStream_t s, const StageHook* h) {
+    const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
+    if (var) run_mode<N, M, kVar, OT>(a, s, h);
+    else if (a.p == N) run_mode<N, M, kFast, OT>(a, s, h);
+    else run_mode<N, M, kInv, OT>(a, s, h);
 }
 
 template <int N, int M>
 static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* h) {
-    const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
-    if (var) run_mode<N, M, kVar>(a, s, h);
-    else if (a.p == N) run_mode<N, M, kFast>(a, s, h);
-    else run_mode<N, M, kInv>(a, s, h);
+    if (a.f32) run_typed<N, M, float>(a, s, h);
+    else run_typed<N, M, double>(a, s, h);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"
+#include "lqt_ws.hpp"
 
 namespace lqt {
 
@@ -115,10 +116,6 @@ WDI void wtrsm_l(int m, int q, const double* R, int ldr, double* B, int ldb, int
 
 // ---- per-instance descriptor helpers -------------------------------------------
 
-WDI const double* step_ptr(const double* base, uint32_t ps, uint32_t bit, int64_t k, int64_t sz) {
-    return (ps & bit) ? base + k * sz : base;
-}
-
 // Layout of the wavefront's LDS slice for maximum dimension N (doubles).
 struct WaveLds {
     int ld;      // leading dimension N + 1
@@ -149,16 +146,6 @@ WDI Slots slots_of(double* base, const WaveLds& w) {
     return s;
 }
 
-WDI int find_instance(const GInst* inst, int ninst, int64_t chunk) {
-    int lo = 0, hi = ninst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (inst[mid].chunk0 <= chunk) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Load a matrix from global (R x Q, row stride gq) into LDS (leading dim ld).
 WDI void gload(int R, int Q, const double* g, int gq, double* l, int ld, int lane) {
     for (int idx = lane; idx < R * Q; idx += kW) {
@@ -175,48 +162,7 @@ WDI void gstore(int R, int Q, const double* l, int ld, double* g, int gq, int la
     }
 }
 
-// Instance constants in the workspace.
-struct CstW {
-    int64_t G, J, W, ST, VT, end;
-};
-
-__host__ __device__ inline CstW cst_layout(int n, int m, int p) {
-    CstW c;
-    c.G = 0;
-    c.J = c.G + (int64_t)n * m;
-    c.W = c.J + (int64_t)n * n;
-    c.ST = c.W + (int64_t)n * p;
-    c.VT = c.ST + (int64_t)n * n;
-    c.end = c.VT + n;
-    return c;
-}
-
-__host__ __device__ inline int64_t elem_doubles(int n) { return 3 * (int64_t)n * n + 2 * n; }
-__host__ __device__ inline int64_t val_doubles(int n) { return (int64_t)n * n + n; }
-
-struct InstWs {
-    double *cst, *agg, *val, *map, *xs;
-};
-
-WDI InstWs inst_ws(const GInst& I) {
-    InstWs w;
-    const int n = I.n;
-    const CstW c = cst_layout(n, I.m, I.p > 0 ? I.p : 1);
-    w.cst = I.ws;
-    w.agg = w.cst + ((c.end + 31) & ~int64_t(31));
-    w.val = w.agg + I.NC * elem_doubles(n);
-    w.map = w.val + (I.NC + 1) * val_doubles(n);
-    w.xs = w.map + I.NC * val_doubles(n);
-    return w;
-}
-
 }  // namespace
-
-int64_t wave_inst_ws_doubles(int n, int m, int p, int64_t NC) {
-    const CstW c = cst_layout(n, m, p > 0 ? p : 1);
-    return ((c.end + 31) & ~int64_t(31)) + NC * elem_doubles(n) + (NC + 1) * val_doubles(n) +
-           NC * val_doubles(n) + NC * n + 32;
-}
 
 namespace {
 
@@ -585,12 +531,12 @@ WDI void tload(int R, int Q, const double* g, int gq, double* l, int lane, doubl
     wsync();
 }
 
-template <int N>
-WDI void tstore(int R, int Q, const double* l, double* g, int gq, int lane) {
+template <int N, typename OT>
+WDI void tstore(int R, int Q, const double* l, OT* g, int gq, int lane) {
     constexpr int ld = TL<N>::ld;
     for (int idx = lane; idx < R * Q; idx += kW) {
         const int r = idx / Q, q = idx - (idx / Q) * Q;
-        g[r * gq + q] = l[r * ld + q];
+        g[r * gq + q] = (OT)l[r * ld + q];
     }
 }
 
@@ -842,7 +788,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     }
 }
 
-template <int N>
+template <int N, typename OT>
 __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int64_t nchunks) {
     extern __shared__ __align__(16) double dyn[];
     constexpr int ld = TL<N>::ld;
@@ -865,6 +811,10 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
     double *Phi = s.m[11], *Ft = s.m[12], *T13 = s.m[13];
     double *v = s.v[0], *cc = s.v[1], *ek = s.v[2], *w = s.v[3], *z = s.v[4], *d = s.v[5];
     double *phi = s.v[6], *ct = s.v[7], *nv = s.v[8], *t9 = s.v[9], *rk = s.v[10];
+    OT* const oS = (OT*)I.S;
+    OT* const oV = (OT*)I.v;
+    OT* const oK = (OT*)I.K;
+    OT* const oD = (OT*)I.d;
     const double* vin = ws.val + (c + 1) * val_doubles(n);
     tload<N>(n, n, vin, n, Sm, lane);
     tvec_load<N>(n, vin + nn, v, lane);
@@ -876,8 +826,8 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
         tload<N>(n, p, ws.cst + cl.W, p, W, lane);
     }
     if (k1 == I.T) {
-        if (I.S) tstore<N>(n, n, Sm, I.S + I.T * nn, n, lane);
-        if (I.v && lane < n) I.v[I.T * n + lane] = v[lane];
+        if (oS) tstore<N>(n, n, Sm, oS + I.T * nn, n, lane);
+        if (oV && lane < n) oV[I.T * n + lane] = (OT)v[lane];
     }
     double fin = 0.0;
     bool ok = true;
@@ -931,10 +881,10 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
         tgemv<N, false>(L, d, ct, 1.0, 0.0, lane);
         if (lane < N) ct[lane] += cc[lane];
         wsync();
-        if (I.S) tstore<N>(n, n, Sm, I.S + k * nn, n, lane);
-        if (I.v && lane < n) I.v[k * n + lane] = v[lane];
-        tstore<N>(m, n, K, I.K + k * m * n, n, lane);
-        if (lane < m) I.d[k * m + lane] = d[lane];
+        if (oS) tstore<N>(n, n, Sm, oS + k * nn, n, lane);
+        if (oV && lane < n) oV[k * n + lane] = (OT)v[lane];
+        tstore<N>(m, n, K, oK + k * m * n, n, lane);
+        if (lane < m) oD[k * m + lane] = (OT)d[lane];
         for (int idx = lane; idx < n * n; idx += kW) fin += Sm[(idx / n) * ld + idx % n];
         if (lane < n) fin += v[lane];
         tgemv<N, false>(Phi, ct, t9, 1.0, 0.0, lane);
@@ -950,7 +900,7 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
     if (!ok && lane == 0) raise(I.status, 3);
 }
 
-template <int N>
+template <int N, typename OT>
 __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64_t nchunks) {
     extern __shared__ __align__(16) double dyn[];
     constexpr int ld = TL<N>::ld;
@@ -967,6 +917,10 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
     const int64_t k1 = (k0 + I.B < I.T) ? k0 + I.B : I.T;
     double *F = s.m[0], *L = s.m[1];
     double *x = s.v[0], *u = s.v[1], *t = s.v[2], *cc = s.v[3];
+    const OT* const iK = (const OT*)I.K;
+    const OT* const iD = (const OT*)I.d;
+    OT* const oX = (OT*)I.x;
+    OT* const oU = (OT*)I.u;
     tvec_load<N>(n, ws.xs + c * n, x, lane);
     double fin = 0.0;
 #pragma unroll 1
@@ -981,15 +935,15 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
         if (lane < N) {
             double a = 0.0;
             if (lane < m) {
-                const double* Kk = I.K + k * m * n;
-                a = I.d[k * m + lane];
-                for (int j = 0; j < n; ++j) a = fma(-Kk[lane * n + j], x[j], a);
+                const OT* Kk = iK + k * m * n;
+                a = (double)iD[k * m + lane];
+                for (int j = 0; j < n; ++j) a = fma(-(double)Kk[lane * n + j], x[j], a);
             }
             u[lane] = a;
         }
         wsync();
-        if (I.x && lane < n) I.x[k * n + lane] = x[lane];
-        if (I.u && lane < m) I.u[k * m + lane] = u[lane];
+        if (oX && lane < n) oX[k * n + lane] = (OT)x[lane];
+        if (oU && lane < m) oU[k * m + lane] = (OT)u[lane];
         if (lane < N) {
             double a = cc[lane];
 #pragma unroll
@@ -1005,7 +959,7 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
         }
         wsync();
     }
-    if (k1 == I.T && I.x && lane < n) I.x[I.T * n + lane] = x[lane];
+    if (k1 == I.T && oX && lane < n) oX[I.T * n + lane] = (OT)x[lane];
     if (__any(!isfinite(fin)) && lane == 0) raise(I.status, 4);
 }
 
@@ -1028,6 +982,7 @@ int tile_class(int need) {
     if (need <= 8) return 8;
     if (need <= 16) return 16;
     if (need <= 32) return 32;
+    if (need <= 64) return 64;
     return 0;
 }
 
@@ -1055,7 +1010,7 @@ struct TileNames<32> {
     static constexpr const char* n[6] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll"};
 };
 
-template <int N>
+template <int N, typename OT>
 static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
                      const StageHook* h) {
     const char* const* nm = TileNames<N>::n;
@@ -1063,8 +1018,8 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
     const size_t glds = wave_lds_bytes(N);
     static bool attr = false;
     if (!attr) {
-        const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N>,
-                            (const void*)t_roll<N>, (const void*)g_prep, (const void*)g_fchain};
+        const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N, OT>,
+                            (const void*)t_roll<N, OT>, (const void*)g_prep, (const void*)g_fchain};
         for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
@@ -1082,7 +1037,7 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
     }
     {
         WStage st(h, nm[3], s);
-        t_final<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+        t_final<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
     if (want_fwd) {
         {
@@ -1090,19 +1045,27 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
             g_fchain<<<ninst, kW, glds, s>>>(d_inst, ninst, N);
         }
         WStage st(h, nm[5], s);
-        t_roll<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+        t_roll<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
 }
 
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
-                      const StageHook* h) {
+template <typename OT>
+static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
+                             const StageHook* h) {
     switch (N) {
-        case 8: run_tile<8>(d_inst, ninst, nchunks, want_fwd, s, h); break;
-        case 16: run_tile<16>(d_inst, ninst, nchunks, want_fwd, s, h); break;
-        case 32: run_tile<32>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
+                      hipStream_t s, const StageHook* h) {
+    if (N == 64) return block_solve(d_inst, ninst, nchunks, want_fwd, f32, s, h);
+    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, want_fwd, s, h)
+               : tile_typed<double>(N, d_inst, ninst, nchunks, want_fwd, s, h);
 }
 
 }  // namespace lqt

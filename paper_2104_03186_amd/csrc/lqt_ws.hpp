@@ -1,0 +1,113 @@
+// Per-instance workspace layout of the chunked pipelines (wavefront size
+// classes 8/16/32 and the workgroup class 64), shared by host and device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lqt_internal.hpp"
+
+namespace lqt {
+
+// Workgroup class: instances with max(n, m, p, pT) above 32 use zero-padded
+// 64 x 64 state matrices and 32-wide control blocks.
+constexpr int kBlockN = 64;
+constexpr int kBlockM = 32;
+
+__host__ __device__ inline int imax4(int a, int b, int c, int d) {
+    const int x = a > b ? a : b, y = c > d ? c : d;
+    return x > y ? x : y;
+}
+
+__host__ __device__ inline bool block_class(int n, int m, int p, int pT) { return imax4(n, m, p, pT) > 32; }
+
+// Instance constants of the wavefront classes (unpadded, row-major).
+struct CstW {
+    int64_t G, J, W, ST, VT, end;
+};
+
+__host__ __device__ inline CstW cst_layout(int n, int m, int p) {
+    CstW c;
+    c.G = 0;
+    c.J = c.G + (int64_t)n * m;
+    c.W = c.J + (int64_t)n * n;
+    c.ST = c.W + (int64_t)n * p;
+    c.VT = c.ST + (int64_t)n * n;
+    c.end = c.VT + n;
+    return c;
+}
+
+// Instance constants of the workgroup class, zero-padded (row stride 64 for
+// n-wide and 32 for m-wide matrices; U is the identity on its padding): F,
+// L, G (G G^T = L U^{-1} L^T), U (symmetrised), J = H^T X H, W = H^T X (n x p),
+// S_T, v_T.
+struct CstB {
+    static constexpr int64_t F = 0;
+    static constexpr int64_t L = F + kBlockN * kBlockN;
+    static constexpr int64_t G = L + kBlockN * kBlockM;
+    static constexpr int64_t U = G + kBlockN * kBlockM;
+    static constexpr int64_t J = U + kBlockM * kBlockM;
+    static constexpr int64_t W = J + kBlockN * kBlockN;
+    static constexpr int64_t ST = W + kBlockN * kBlockN;
+    static constexpr int64_t VT = ST + kBlockN * kBlockN;
+    static constexpr int64_t end = VT + kBlockN;
+};
+
+// Element, value and map records: dimension n (wavefront classes) or the
+// padded 64 (workgroup class).
+__host__ __device__ inline int64_t elem_doubles(int n) { return 3 * (int64_t)n * n + 2 * n; }
+__host__ __device__ inline int64_t val_doubles(int n) { return (int64_t)n * n + n; }
+
+// Record dimension and constants size of an instance.
+__host__ __device__ inline int ws_dim(int n, int m, int p, int pT) { return block_class(n, m, p, pT) ? kBlockN : n; }
+__host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int pT) {
+    const int64_t e = block_class(n, m, p, pT) ? CstB::end : cst_layout(n, m, p > 0 ? p : 1).end;
+    return (e + 31) & ~int64_t(31);
+}
+
+// cst | agg[NC] (chunk elements) | val[NC + 1] (value at chunk starts and T)
+//     | map[NC] (chunk affine maps) | xs[NC] (state at chunk starts)
+__host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int pT, int64_t NC) {
+    const int d = ws_dim(n, m, p, pT);
+    return ws_cst_doubles(n, m, p, pT) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
+           NC * d + 32;
+}
+
+struct InstWs {
+    double *cst, *agg, *val, *map, *xs;
+    int d;  // record dimension
+};
+
+__device__ inline InstWs inst_ws(const GInst& I) {
+    InstWs w;
+    const int d = ws_dim(I.n, I.m, I.p, I.pT);
+    w.d = d;
+    w.cst = I.ws;
+    w.agg = w.cst + ws_cst_doubles(I.n, I.m, I.p, I.pT);
+    w.val = w.agg + I.NC * elem_doubles(d);
+    w.map = w.val + (I.NC + 1) * val_doubles(d);
+    w.xs = w.map + I.NC * val_doubles(d);
+    return w;
+}
+
+__device__ inline const double* step_ptr(const double* base, uint32_t ps, uint32_t bit, int64_t k, int64_t sz) {
+    return (ps & bit) ? base + k * sz : base;
+}
+
+// Instance owning flat chunk index `chunk` (instances sorted by chunk0).
+__device__ inline int find_instance(const GInst* inst, int ninst, int64_t chunk) {
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].chunk0 <= chunk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// First failure wins.
+__device__ inline void raise_status(int32_t* st, int32_t code) {
+    if (st) atomicCAS(st, 0, code);
+}
+
+}  // namespace lqt

@@ -1,0 +1,221 @@
+"""GPU tests of the serving interface (lqt_submit / lqt_poll): continuous
+batching, admission by device-memory footprint, queue limits, isolation.
+
+Every served result is checked against the FP64 oracle (MIXED tolerance
+1e-5) and against the same instance solved alone by lqt_solve, bit for bit:
+batching must never change a result.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_03186_amd import inputs
+from tests.helpers import FAMILIES, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2104_03186_amd import api as _api
+
+    return _api
+
+
+@pytest.fixture(autouse=True)
+def _env():
+    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_CHUNK", "LQT_PATH")}
+    yield
+    for k in saved:
+        if saved[k] is not None:
+            os.environ[k] = saved[k]
+
+
+def served_request(n, T, i):
+    """Request generator of the serving workload: nx = n, nu = ceil(n / 2),
+    diagonal costs and a random-walk reference."""
+    return inputs.diag_problem(n, (n + 1) // 2, T, 4, i)
+
+
+def out_for(api, p):
+    import torch
+
+    return api.DeviceOutputs(p.n, p.m, p.T, dtype=torch.float32)
+
+
+def wait_all(plan, tickets, limit=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < limit, f"{len(tickets) - len(done)} requests still running after {limit} s"
+        for t in tickets:
+            if t not in done:
+                st = plan.poll(t)
+                if st is not None:
+                    done[t] = st
+    return [done[t] for t in tickets]
+
+
+def solve_alone(api, p):
+    import torch
+
+    plan = api.Plan(32, 16, prec="mixed")
+    do = out_for(api, p)
+    plan.solve([api.DeviceProblem(p)], [do])
+    torch.cuda.synchronize()
+    plan.close()
+    return do.host()
+
+
+def check(got, ref):
+    errs = {f: rel(got[f], ref[f]) for f in got}
+    bad = {f: e for f, e in errs.items() if not e <= TOL}
+    assert not bad, f"rel errors above {TOL}: {bad}"
+
+
+def test_served_equals_alone_and_oracle(api):
+    rng = np.random.default_rng(3)
+    probs = []
+    for i in range(28):
+        n = int(rng.integers(4, 33))
+        T = int(np.exp(rng.uniform(np.log(64), np.log(1500 if n > 16 else 5000))))
+        probs.append(served_request(n, T, i))
+    probs.append(inputs.tracking_problem(n=4, m=2, T=9000, instance=7))  # lane-per-element path
+    _say("served mix of", len(probs), "requests")
+    plan = api.Plan(32, 16, prec="mixed")
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [out_for(api, p) for p in probs]
+    tickets = [plan.submit(dp, do) for dp, do in zip(dps, dos)]
+    status = wait_all(plan, tickets)
+    st = plan.serve_stats()
+    _say("stats", st)
+    plan.close()
+    assert all(s == 0 for s in status), status
+    assert st["submitted"] == len(probs) and st["completed"] == len(probs)
+    assert st["running_batches"] == 0 and st["pool_in_use"] == 0
+    for i, (p, do) in enumerate(zip(probs, dos)):
+        got = do.host()
+        check(got, oracle.solve(p))
+        alone = solve_alone(api, p)
+        for f in FAMILIES:
+            assert np.array_equal(got[f], alone[f]), (i, f)
+
+
+def test_arrivals_overlap_running_batches(api):
+    # a long request occupies one stream; requests that arrive while it runs
+    # are launched on the other streams at once and finish first
+    long_p = served_request(32, 30000, 100)
+    short = [served_request(8, 200, 101 + i) for i in range(6)]
+    plan = api.Plan(32, 16, prec="mixed")
+    dl, ol = api.DeviceProblem(long_p), out_for(api, long_p)
+    ds = [api.DeviceProblem(p) for p in short]
+    os_ = [out_for(api, p) for p in short]
+    _say("long request then arrivals")
+    tl = plan.submit(dl, ol)
+    ts = []
+    for d, o in zip(ds, os_):
+        ts.append(plan.submit(d, o))
+        time.sleep(0.002)
+    short_status = wait_all(plan, ts)
+    long_done_first = plan.poll(tl)
+    long_status = wait_all(plan, [tl])[0] if long_done_first is None else long_done_first
+    st = plan.serve_stats()
+    _say("stats", st, "long finished before the short ones:", long_done_first is not None)
+    plan.close()
+    assert all(s == 0 for s in short_status) and long_status == 0
+    assert st["max_running_batches"] >= 2, st
+    assert st["batches"] >= 2, st
+    for p, o in zip(short, os_):
+        check(o.host(), oracle.solve(p))
+
+
+def test_memory_admission(api):
+    probs = [served_request(12, 3000, 200 + i) for i in range(6)]
+    probe = api.Plan(32, 16, prec="mixed")
+    dp0, do0 = api.DeviceProblem(probs[0]), out_for(api, probs[0])
+    wait_all(probe, [probe.submit(dp0, do0)])
+    one = probe.serve_stats()["pool_peak"]
+    probe.close()
+    assert one > 0
+    budget = int(2.5 * one)
+    _say("admission: one request needs", one, "bytes; pool", budget)
+    plan = api.Plan(32, 16, prec="mixed", hbm_budget_bytes=budget)
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [out_for(api, p) for p in probs]
+    tickets = [plan.submit(dp, do) for dp, do in zip(dps, dos)]
+    status = wait_all(plan, tickets)
+    st = plan.serve_stats()
+    _say("stats", st)
+    plan.close()
+    assert all(s == 0 for s in status)
+    assert st["pool_peak"] <= budget and st["max_batch"] <= 2 and st["batches"] >= 3, st
+    for p, do in zip(probs, dos):
+        got = do.host()
+        alone = solve_alone(api, p)
+        for f in FAMILIES:
+            assert np.array_equal(got[f], alone[f])
+    check(dos[-1].host(), oracle.solve(probs[-1]))
+
+
+def test_request_larger_than_pool(api):
+    from paper_2104_03186_amd import _lib
+
+    p = served_request(16, 20000, 300)
+    plan = api.Plan(32, 16, prec="mixed", hbm_budget_bytes=1 << 16)  # the request needs about 0.9 MB
+    _say("request above the pool size")
+    with pytest.raises(_lib.LQTError) as e:
+        plan.submit(api.DeviceProblem(p), out_for(api, p))
+    assert e.value.code == _lib.ENOMEM
+    assert plan.serve_stats()["submitted"] == 0
+    plan.close()
+
+
+def test_queue_limit(api):
+    from paper_2104_03186_amd import _lib
+
+    a = served_request(32, 30000, 400)
+    b = served_request(8, 100, 401)
+    plan = api.Plan(32, 16, prec="mixed", max_inflight=1)
+    da, oa, db, ob = api.DeviceProblem(a), out_for(api, a), api.DeviceProblem(b), out_for(api, b)
+    _say("queue limit 1")
+    ta = plan.submit(da, oa)
+    with pytest.raises(_lib.LQTError) as e:
+        plan.submit(db, ob)
+    assert e.value.code == _lib.EBUSY
+    assert wait_all(plan, [ta]) == [0]
+    tb = plan.submit(db, ob)
+    assert wait_all(plan, [tb]) == [0]
+    plan.close()
+    check(ob.host(), oracle.solve(b))
+
+
+def test_failure_isolated_in_batch(api):
+    good = [served_request(6, 300, 500 + i) for i in range(3)]
+    bad = served_request(6, 300, 510)
+    bad.U = -np.eye(bad.m)
+    probs = [good[0], bad, good[1], good[2]]
+    plan = api.Plan(32, 16, prec="mixed")
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [out_for(api, p) for p in probs]
+    _say("bad request inside a batch")
+    tickets = [plan.submit(dp, do) for dp, do in zip(dps, dos)]
+    status = wait_all(plan, tickets)
+    plan.close()
+    assert status == [0, 3, 0, 0]
+    assert int(dos[1].status.item()) == 3
+    for i in (0, 2, 3):
+        check(dos[i].host(), oracle.solve(probs[i]))
