@@ -52,7 +52,8 @@ struct GInst {
     int32_t B;        // steps per chunk
     int64_t NC;       // chunks
     int64_t chunk0;   // flat index of the first chunk over the launch
-    double* ws;       // instance workspace (wave_inst_ws_doubles)
+    double* ws;       // instance workspace (ws_doubles)
+    int32_t eng;      // 0: wavefront engine; else padded dimension of the workgroup engine
 };
 
 size_t wave_lds_bytes(int nmax);
@@ -63,9 +64,10 @@ int tile_class(int need);
 size_t tile_lds_bytes(int N);
 hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h);
-// Workgroup class (N = 64): n, p, pT <= 64, m <= 32, time-invariant except c.
-hipError_t block_solve(const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32, hipStream_t s,
-                       const StageHook* h);
+// Workgroup engines (N = 16, 32, 64; time-invariant except c; class 64:
+// n, p, pT <= 64 and m <= 32).
+hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
+                       hipStream_t s, const StageHook* h);
 
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);

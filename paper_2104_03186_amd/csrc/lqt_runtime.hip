@@ -47,6 +47,24 @@ Path path_of(const lqt_problem& p) {
     return (small_ok && p.T >= kSmallMinT) ? Path::Small : Path::Wave;
 }
 
+// Engine of a chunked-path instance: the workgroup engine (padded dimension
+// 16, 32 or 64) for time-invariant instances (only c and r may vary per step)
+// of the classes 16 and 32 and for every class-64 instance, else the
+// wavefront engine (0).  LQT_BLOCK=0 keeps the classes 16 and 32 on the
+// wavefront engine (tests).
+int tile_class_of(const lqt_problem& p) {
+    return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
+}
+
+int eng_of(const lqt_problem& p) {
+    const int cls = tile_class_of(p);
+    if (cls == 64) return 64;
+    const char* e = getenv("LQT_BLOCK");
+    const bool allow = !(e && !strcmp(e, "0"));
+    if (allow && (cls == 16 || cls == 32) && !(p.per_step & ~(uint32_t)LQT_PS_c)) return cls;
+    return 0;
+}
+
 int wave_chunk(int64_t T) {
     if (const char* e = getenv("LQT_WCHUNK")) {
         int b = atoi(e);
@@ -214,7 +232,7 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
 size_t wave_bytes(const lqt_problem& p) {
     const int B = wave_chunk(p.T);
     const int64_t NC = (p.T + B - 1) / B;
-    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, p.nyT, NC) * sizeof(double));
+    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(p), NC) * sizeof(double));
 }
 size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
     return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
@@ -334,10 +352,8 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     // partition by path; wavefront instances ordered by size class
     std::vector<int> small, wave;
     for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
-    auto cls = [&](int i) {
-        const lqt_problem& p = probs[i];
-        return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
-    };
+    // launch groups: (size class, engine)
+    auto cls = [&](int i) { return 2 * tile_class_of(probs[i]) + (eng_of(probs[i]) ? 1 : 0); };
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
     // workspace: [small-path region (largest small instance)] [wave region] [instance table]
     BatchSize bs;
@@ -392,6 +408,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         g.chunk0 = chunk0;
         chunk0 += g.NC;
         g.ws = (double*)(wbase + ws_off[j]);
+        g.eng = eng_of(p);
         want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
     }
     lqt::GInst* d_inst = (lqt::GInst*)(wbase + bs.wave);
@@ -411,8 +428,13 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
             fwd = fwd || want_fwd_c[j1];
             ++j1;
         }
-        hipError_t e = lqt::tile_solve(cls(wave[j0]), d_inst + j0, (int)(j1 - j0), nch, fwd,
-                                       plan->desc.prec == LQT_PREC_MIXED, s, plan->prof.on ? &hook : nullptr);
+        const lqt_problem& p0 = probs[wave[j0]];
+        const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
+        const int eng = eng_of(p0);
+        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
+                                              plan->prof.on ? &hook : nullptr)
+                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
+                                             plan->prof.on ? &hook : nullptr);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
         j0 = j1;
     }
@@ -617,7 +639,10 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
         {
             const int64_t B = wave_chunk(desc->max_steps);
             const int64_t NC = (desc->max_steps + B - 1) / B;
-            const size_t w = (size_t)lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, desc->max_nx, NC) * 8 +
+            const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
+            const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC),
+                                        lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC));
+            const size_t w = (size_t)wd * 8 +
                              (size_t)desc->max_steps * (desc->max_nu * desc->max_nx + desc->max_nu) * 8 + 4096;
             need = std::max(need, w);
         }

@@ -1063,7 +1063,6 @@ static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchu
 
 hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h) {
-    if (N == 64) return block_solve(d_inst, ninst, nchunks, want_fwd, f32, s, h);
     return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, want_fwd, s, h)
                : tile_typed<double>(N, d_inst, ninst, nchunks, want_fwd, s, h);
 }

@@ -9,8 +9,8 @@
 
 namespace lqt {
 
-// Workgroup class: instances with max(n, m, p, pT) above 32 use zero-padded
-// 64 x 64 state matrices and 32-wide control blocks.
+// Dense workgroup class: instances with max(n, m, p, pT) above 32 use
+// zero-padded 64 x 64 state matrices and 32-wide control blocks.
 constexpr int kBlockN = 64;
 constexpr int kBlockM = 32;
 
@@ -37,39 +37,51 @@ __host__ __device__ inline CstW cst_layout(int n, int m, int p) {
     return c;
 }
 
-// Instance constants of the workgroup class, zero-padded (row stride 64 for
-// n-wide and 32 for m-wide matrices; U is the identity on its padding): F,
-// L, G (G G^T = L U^{-1} L^T), U (symmetrised), J = H^T X H, W = H^T X (n x p),
-// S_T, v_T.
-struct CstB {
+// Instance constants of a workgroup engine with padded dimensions N (state)
+// and M (control), zero-padded (row stride N for n-wide and M for m-wide
+// matrices; U is the identity on its padding): F, L, G (G G^T = L U^{-1} L^T),
+// U (symmetrised), J = H^T X H, W = H^T X (n x p), S_T, v_T.
+template <int N, int M>
+struct CstBT {
     static constexpr int64_t F = 0;
-    static constexpr int64_t L = F + kBlockN * kBlockN;
-    static constexpr int64_t G = L + kBlockN * kBlockM;
-    static constexpr int64_t U = G + kBlockN * kBlockM;
-    static constexpr int64_t J = U + kBlockM * kBlockM;
-    static constexpr int64_t W = J + kBlockN * kBlockN;
-    static constexpr int64_t ST = W + kBlockN * kBlockN;
-    static constexpr int64_t VT = ST + kBlockN * kBlockN;
-    static constexpr int64_t end = VT + kBlockN;
+    static constexpr int64_t L = F + N * N;
+    static constexpr int64_t G = L + N * M;
+    static constexpr int64_t U = G + N * M;
+    static constexpr int64_t J = U + M * M;
+    static constexpr int64_t W = J + N * N;
+    static constexpr int64_t ST = W + N * N;
+    static constexpr int64_t VT = ST + N * N;
+    static constexpr int64_t end = VT + N;
 };
+
+// Engine of an instance: 0 = wavefront engine (records of dimension n), or
+// the padded state dimension (16, 32, 64) of a workgroup engine.
+__host__ __device__ inline int64_t eng_cst_end(int eng) {
+    switch (eng) {
+        case 16: return CstBT<16, 16>::end;
+        case 32: return CstBT<32, 32>::end;
+        case 64: return CstBT<64, 32>::end;
+    }
+    return 0;
+}
 
 // Element, value and map records: dimension n (wavefront classes) or the
 // padded 64 (workgroup class).
 __host__ __device__ inline int64_t elem_doubles(int n) { return 3 * (int64_t)n * n + 2 * n; }
 __host__ __device__ inline int64_t val_doubles(int n) { return (int64_t)n * n + n; }
 
-// Record dimension and constants size of an instance.
-__host__ __device__ inline int ws_dim(int n, int m, int p, int pT) { return block_class(n, m, p, pT) ? kBlockN : n; }
-__host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int pT) {
-    const int64_t e = block_class(n, m, p, pT) ? CstB::end : cst_layout(n, m, p > 0 ? p : 1).end;
+// Record dimension and constants size of an instance on engine `eng`.
+__host__ __device__ inline int ws_dim(int n, int eng) { return eng ? eng : n; }
+__host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int eng) {
+    const int64_t e = eng ? eng_cst_end(eng) : cst_layout(n, m, p > 0 ? p : 1).end;
     return (e + 31) & ~int64_t(31);
 }
 
 // cst | agg[NC] (chunk elements) | val[NC + 1] (value at chunk starts and T)
 //     | map[NC] (chunk affine maps) | xs[NC] (state at chunk starts)
-__host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int pT, int64_t NC) {
-    const int d = ws_dim(n, m, p, pT);
-    return ws_cst_doubles(n, m, p, pT) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
+__host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int64_t NC) {
+    const int d = ws_dim(n, eng);
+    return ws_cst_doubles(n, m, p, eng) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
            NC * d + 32;
 }
 
@@ -80,10 +92,10 @@ struct InstWs {
 
 __device__ inline InstWs inst_ws(const GInst& I) {
     InstWs w;
-    const int d = ws_dim(I.n, I.m, I.p, I.pT);
+    const int d = ws_dim(I.n, I.eng);
     w.d = d;
     w.cst = I.ws;
-    w.agg = w.cst + ws_cst_doubles(I.n, I.m, I.p, I.pT);
+    w.agg = w.cst + ws_cst_doubles(I.n, I.m, I.p, I.eng);
     w.val = w.agg + I.NC * elem_doubles(d);
     w.map = w.val + (I.NC + 1) * val_doubles(d);
     w.xs = w.map + I.NC * val_doubles(d);

@@ -1,5 +1,6 @@
-"""GPU parity of the wavefront-per-chunk path (general n) against the FP64
-oracle, batched solves, and batch independence.
+"""GPU parity of the chunked paths for n up to 32 (wavefront engine, and the
+workgroup engine for time-invariant instances of the classes 16 and 32)
+against the FP64 oracle, batched solves, and batch independence.
 
 Tolerance: relative Frobenius error <= 1e-10 per output family (FP64).
 """
@@ -40,10 +41,15 @@ def plan(api):
     p.close()
 
 
-@pytest.fixture(autouse=True)
-def _wave_env():
-    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_PATH")}
+@pytest.fixture(autouse=True, params=["workgroup", "wavefront"])
+def _wave_env(request):
+    """Every test runs twice: time-invariant instances of the classes 16 and
+    32 on the workgroup engine (default routing) and on the wavefront
+    engine (LQT_BLOCK=0)."""
+    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_PATH", "LQT_BLOCK")}
     os.environ["LQT_PATH"] = "wave"
+    if request.param == "wavefront":
+        os.environ["LQT_BLOCK"] = "0"
     yield
     for k, v in saved.items():
         os.environ.pop(k, None)
