@@ -138,6 +138,19 @@ lqt_status lqt_plan(const lqt_plan_desc *desc, lqt_plan_t *out);
 lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
                      int32_t count, void *stream);
 
+/* Autotuner.  Times the given instances (solved into outs, stream-ordered on
+ * `stream`, synchronous) with several chunk lengths for every launch group
+ * (size class 8, 16, 32, 64 x wavefront / workgroup engine) present, and
+ * keeps the fastest for later solves of this plan: the chunk length of an
+ * instance is about T / div steps (16 <= length <= 256) with div in
+ * {16, 32, 64, 128, 256} (default 64).  chosen (may be NULL) receives the
+ * div of the 8 groups (index 2 * class_index + engine).  The chunking changes
+ * the association order of the scan, so results of a tuned plan differ from
+ * an untuned one by rounding only; within a plan a result never depends on
+ * the batch it is solved in. */
+lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
+                    int32_t count, void *stream, int32_t *chosen);
+
 /* Serving interface (continuous batching).  lqt_submit queues one instance
  * and returns at once with *ticket.  Queued requests are launched in FIFO
  * order as batches: whenever one of the plan's serving streams is idle, the

@@ -19,7 +19,7 @@ STATUS_NAMES = {OK: "LQT_OK", EINVAL: "LQT_EINVAL", ENOMEM: "LQT_ENOMEM", ENOTPD
 PREC_FP64, PREC_MIXED = 0, 1
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
-EXPORTED = ("lqt_plan", "lqt_solve", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
+EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
             "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error")
 
 _vp = ctypes.c_void_p
@@ -75,6 +75,9 @@ def load() -> ctypes.CDLL:
     lib.lqt_plan.restype = ctypes.c_int
     lib.lqt_solve.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.c_int32, _vp]
     lib.lqt_solve.restype = ctypes.c_int
+    lib.lqt_tune.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.c_int32, _vp,
+                             ctypes.POINTER(ctypes.c_int32)]
+    lib.lqt_tune.restype = ctypes.c_int
     lib.lqt_submit.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.POINTER(ctypes.c_uint64)]
     lib.lqt_submit.restype = ctypes.c_int
     lib.lqt_poll.argtypes = [_vp, ctypes.c_uint64]

@@ -98,6 +98,22 @@ class Plan:
         sp = ctypes.c_void_p(stream.cuda_stream)
         _lib.check(_lib.load().lqt_solve(self._h, P, O, n, sp), self._h)
 
+    def tune(self, probs: Sequence[DeviceProblem], outs: Sequence[DeviceOutputs], stream=None) -> List[int]:
+        """Pick the chunk length of every launch group present from timed
+        solves of these instances (lqt_tune); returns the 8 chosen divisors."""
+        if len(probs) != len(outs):
+            raise ValueError("probs and outs differ in length")
+        for o in outs:
+            self._check_dtype(o)
+        n = len(probs)
+        P = (_lib.Problem * max(n, 1))(*[p.struct() for p in probs])
+        O = (_lib.Outputs * max(n, 1))(*[o.struct() for o in outs])
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        ch = (ctypes.c_int32 * 8)()
+        _lib.check(_lib.load().lqt_tune(self._h, P, O, n, ctypes.c_void_p(stream.cuda_stream), ch), self._h)
+        return list(ch)
+
     def _check_dtype(self, out: DeviceOutputs) -> None:
         want = torch.float64 if self.prec == "fp64" else torch.float32
         for k, t in out.t.items():

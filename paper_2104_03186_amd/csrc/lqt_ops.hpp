@@ -316,8 +316,9 @@ LQT_DI void anchor(const Elem<N>& x, double* Sv, double* v) {
 //   S' = F^T S F - (R^{-1} L^T S F)^T (R^{-1} L^T S F) + H^T X H,
 //   v' = F^T (v - S c) - K^T L^T (v - S c) + H^T X r.
 // Also returns the closed-loop map Ft = F - L K, ct = c + L d (Section IV-C).
-// Returns false when M_k is not positive definite.
-template <int N, int M>
+// Returns false when M_k is not positive definite.  HASC = false: c = 0
+// (c is not read).
+template <int N, int M, bool HASC = true>
 LQT_DI bool riccati_step(const double* F, const double* c, const double* L, const double* Uu,
                          const double* Js, const double* ek, double* Sv, double* v,
                          double* K, double* d, double* Ft, double* ct) {
@@ -339,9 +340,14 @@ LQT_DI bool riccati_step(const double* F, const double* c, const double* L, cons
     lsolve<M, N>(R, rinv, Y);
     LQT_UNROLL for (int i = 0; i < M * N; ++i) K[i] = Y[i];
     ltsolve<M, N>(R, rinv, K);
-    double w[N], Sc[N], z[M];
-    smv<N>(Sv, c, Sc);
-    LQT_UNROLL for (int i = 0; i < N; ++i) w[i] = v[i] - Sc[i];
+    double w[N], z[M];
+    if constexpr (HASC) {
+        double Sc[N];
+        smv<N>(Sv, c, Sc);
+        LQT_UNROLL for (int i = 0; i < N; ++i) w[i] = v[i] - Sc[i];
+    } else {
+        LQT_UNROLL for (int i = 0; i < N; ++i) w[i] = v[i];
+    }
     mtv<N, M>(L, w, z);
     LQT_UNROLL for (int p = 0; p < M; ++p) d[p] = z[p];
     lsolve<M, 1>(R, rinv, d);
@@ -366,7 +372,7 @@ LQT_DI bool riccati_step(const double* F, const double* c, const double* L, cons
             LQT_UNROLL for (int p = 0; p < M; ++p) s = fma(-L[i * M + p], K[p * N + j], s);
             Ft[i * N + j] = s;
         }
-        double s = c[i];
+        double s = HASC ? c[i] : 0.0;
         LQT_UNROLL for (int p = 0; p < M; ++p) s = fma(L[i * M + p], d[p], s);
         ct[i] = s;
     }

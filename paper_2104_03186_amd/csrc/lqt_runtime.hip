@@ -65,13 +65,27 @@ int eng_of(const lqt_problem& p) {
     return 0;
 }
 
-int wave_chunk(int64_t T) {
+// Chunk length of a chunked-path instance: about `div` chunks per instance
+// (default 64; lqt_tune picks div per launch group), between 16 and 256
+// steps.  LQT_WCHUNK fixes the length (tests).
+constexpr int kDefaultDiv = 64;
+constexpr int kTuneDivs[] = {16, 32, 64, 128, 256};
+
+int wave_chunk(int64_t T, int div = kDefaultDiv) {
     if (const char* e = getenv("LQT_WCHUNK")) {
         int b = atoi(e);
         if (b >= 1 && b <= 4096) return b;
     }
-    int64_t b = (T + 63) / 64;
+    int64_t b = (T + div - 1) / div;
     return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
+}
+
+// Launch group of a chunked-path instance: size class (8, 16, 32, 64) and
+// engine (wavefront / workgroup), as an index 0..7.
+int group_key(const lqt_problem& p) {
+    const int cls = tile_class_of(p);
+    const int ci = cls <= 8 ? 0 : (cls <= 16 ? 1 : (cls <= 32 ? 2 : 3));
+    return 2 * ci + (eng_of(p) ? 1 : 0);
 }
 
 thread_local std::string g_create_error;
@@ -165,6 +179,7 @@ struct lqt_plan_s {
     size_t live = 0;                          // queued + running requests
     uint64_t next_ticket = 1;
     lqt_serve_stats stats{};
+    int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
 };
 
 namespace {
@@ -227,10 +242,15 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
     return L;
 }
 
+int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
+    const int d = plan ? plan->tune_div[group_key(p)] : 0;
+    return wave_chunk(p.T, d > 0 ? d : kDefaultDiv);
+}
+
 // Workspace of one wavefront-path instance, and of its K, d scratch when the
 // caller does not take K and d.
-size_t wave_bytes(const lqt_problem& p) {
-    const int B = wave_chunk(p.T);
+size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
+    const int B = chunk_for(plan, p);
     const int64_t NC = (p.T + B - 1) / B;
     return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(p), NC) * sizeof(double));
 }
@@ -242,13 +262,15 @@ size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
 // another in one region (the largest), each wavefront-path instance has its
 // own region, then the instance table.
 struct BatchSize {
+    lqt_plan_t plan = nullptr;
     size_t small = 0, wave = 0;
     size_t nwave = 0;
+    explicit BatchSize(lqt_plan_t pl) : plan(pl) {}
     void add(const lqt_problem& p, const lqt_outputs& o) {
         if (path_of(p) == Path::Small) {
             small = std::max(small, align_up(layout_for(p, !o.K, !o.d).total));
         } else {
-            wave += wave_bytes(p) + wave_kd_bytes(p, o);
+            wave += wave_bytes(plan, p) + wave_kd_bytes(p, o);
             ++nwave;
         }
     }
@@ -356,13 +378,13 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     auto cls = [&](int i) { return 2 * tile_class_of(probs[i]) + (eng_of(probs[i]) ? 1 : 0); };
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
     // workspace: [small-path region (largest small instance)] [wave region] [instance table]
-    BatchSize bs;
+    BatchSize bs(plan);
     for (int i = 0; i < count; ++i) bs.add(probs[i], outs[i]);
     std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
     size_t wave_need = 0;
     for (size_t j = 0; j < wave.size(); ++j) {
         ws_off[j] = (int64_t)wave_need;
-        wave_need += wave_bytes(probs[wave[j]]);
+        wave_need += wave_bytes(plan, probs[wave[j]]);
         kd_off[j] = (int64_t)wave_need;
         wave_need += wave_kd_bytes(probs[wave[j]], outs[wave[j]]);
     }
@@ -403,7 +425,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         g.status = status_override ? status_override[wave[j]] : o.status;
         g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
         g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-        g.B = wave_chunk(p.T);
+        g.B = chunk_for(plan, p);
         g.NC = (p.T + g.B - 1) / g.B;
         g.chunk0 = chunk0;
         chunk0 += g.NC;
@@ -456,8 +478,8 @@ void arena_release(Arena& A) {
 // the device; a finished batch returns its range and slot, and the next batch
 // takes whatever has arrived in the meantime.
 
-size_t serve_bytes(const lqt_problem& p, const lqt_outputs& o) {
-    BatchSize b;
+size_t serve_bytes(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o) {
+    BatchSize b(plan);
     b.add(p, o);
     return b.total();
 }
@@ -547,10 +569,10 @@ lqt_status serve_pump(lqt_plan_t plan) {
         if (plan->pending.empty()) break;
         if (s.busy) continue;
         const size_t room = pool_largest(plan);
-        BatchSize bs;
+        BatchSize bs(plan);
         size_t take = 0;
         while (take < plan->pending.size() && take < (size_t)kServeBatchMax) {
-            BatchSize t = bs;
+            BatchSize t = bs;  // copy
             t.add(plan->pending[take].p, plan->pending[take].o);
             if (t.total() > room) break;
             bs = t;
@@ -672,6 +694,59 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
     return solve_all(plan, plan->main, probs, outs, count, (hipStream_t)stream, nullptr);
 }
 
+lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count, void* stream,
+                    int32_t* chosen) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_tune: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (count < 0 || (count > 0 && (!probs || !outs))) return fail(plan, LQT_EINVAL, "lqt_tune: bad count/arrays");
+    for (int i = 0; i < count; ++i) {
+        lqt_status st = validate(plan, probs[i], outs[i], i);
+        if (st != LQT_OK) return st;
+    }
+    if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(plan, LQT_EHIP, "lqt_tune: event creation failed");
+    lqt_status st = LQT_OK;
+    for (int key = 0; key < 8 && st == LQT_OK; ++key) {
+        std::vector<lqt_problem> ps;
+        std::vector<lqt_outputs> os;
+        for (int i = 0; i < count; ++i)
+            if (path_of(probs[i]) == Path::Wave && group_key(probs[i]) == key) {
+                ps.push_back(probs[i]);
+                os.push_back(outs[i]);
+            }
+        if (ps.empty()) continue;
+        float best = 0.f;
+        int best_div = kDefaultDiv;
+        for (int div : kTuneDivs) {
+            plan->tune_div[key] = div;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && st == LQT_OK; ++rep) {  // the first run warms up
+                (void)hipEventRecord(e0, s);
+                st = solve_all(plan, plan->main, ps.data(), os.data(), (int32_t)ps.size(), s, nullptr);
+                (void)hipEventRecord(e1, s);
+                if (st == LQT_OK && hipEventSynchronize(e1) != hipSuccess)
+                    st = fail(plan, LQT_EHIP, "lqt_tune: timing failed");
+                if (st == LQT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (st != LQT_OK) break;
+            if (best == 0.f || ms < best) {
+                best = ms;
+                best_div = div;
+            }
+        }
+        plan->tune_div[key] = best_div;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (chosen)
+        for (int key = 0; key < 8; ++key) chosen[key] = plan->tune_div[key] > 0 ? plan->tune_div[key] : kDefaultDiv;
+    return st;
+}
+
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, uint64_t* ticket) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_submit: NULL plan");
     if (!prob || !out || !ticket) return fail(plan, LQT_EINVAL, "lqt_submit: NULL argument");
@@ -682,7 +757,7 @@ lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_output
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
     st = serve_init(plan);
     if (st != LQT_OK) return st;
-    const size_t need = serve_bytes(*prob, *out);
+    const size_t need = serve_bytes(plan, *prob, *out);
     if (need > plan->pool_size)
         return fail(plan, LQT_ENOMEM, "lqt_submit: request needs %zu device bytes, the serving pool holds %zu", need,
                     plan->pool_size);

@@ -23,6 +23,8 @@
 //                 with u_k = -K_k x_k + d_k (writes x, u).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lqt_internal.hpp"
 #include "lqt_ops.hpp"
 
@@ -311,18 +313,31 @@ LQT_DI void lds_put_row(OT* lds, int lane, const double* v) {
 }
 
 // rows (cw0 + rec) * B + j, valid when cw0 + rec < NC and the row < T
-template <int R, typename OT>
+// (CHECK = false: the caller knows every row of the wavefront is valid)
+template <int R, bool CHECK = true, typename OT>
 LQT_DI void wave_store_rows(const OT* lds, OT* g, int64_t cw0, int64_t NC, int B, int j, int64_t T, int lane) {
     constexpr int st = Staged<R>::stride;
     constexpr int W = PieceW<OT, R>::W;
     constexpr int P = R / W;  // pieces per row
-    LQT_UNROLL for (int it = 0; it < P; ++it) {
-        const int piece = it * kWave + lane;
-        const int rec = piece / P;
-        const int off = (piece - rec * P) * W;
-        const int64_t c = cw0 + rec;
-        const int64_t row = c * B + j;
-        if (c < NC && row < T) put_piece<W>(g + row * R + off, lds + rec * st + off);
+    if constexpr (!CHECK && kWave % P == 0) {
+        // piece it of lane l belongs to record it * (64 / P) + l / P: one
+        // per-lane base address and a uniform stride per piece
+        constexpr int RPI = kWave / P;  // records per piece index
+        const int rec0 = lane / P;
+        const int off = (lane - rec0 * P) * W;
+        OT* gb = g + ((cw0 + rec0) * B + j) * R + off;
+        const int64_t stride = (int64_t)RPI * B * R;
+        LQT_UNROLL for (int it = 0; it < P; ++it)
+            put_piece<W>(gb + it * stride, lds + (it * RPI + rec0) * st + off);
+    } else {
+        LQT_UNROLL for (int it = 0; it < P; ++it) {
+            const int piece = it * kWave + lane;
+            const int rec = piece / P;
+            const int off = (piece - rec * P) * W;
+            const int64_t c = cw0 + rec;
+            const int64_t row = c * B + j;
+            if (!CHECK || (c < NC && row < T)) put_piece<W>(g + row * R + off, lds + rec * st + off);
+        }
     }
 }
 
@@ -499,13 +514,22 @@ LQT_DI void load_inv_shared(const SmallArgs& a, InvShared<N, M>& sh) {
     if (t < N * N) sh.W[t] = (a.p == N) ? a.cst[CL::W + t] : 0.0;
 }
 
-template <int N, int M, int MODE, bool ALL, typename OT>
+template <int N, int M, int MODE, bool ALL, typename OT, bool HASC>
 __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
     using S = Sym<N>;
     using CL = CstLayout<N, M>;
     constexpr int VS = S::size + N;
     __shared__ __align__(16) OT shS[kBlock / kWave][Staged<N * N>::elems];
-    __shared__ __align__(16) OT shK[kBlock / kWave][Staged<M * N>::elems];
+    // Per-wavefront staging of K rows, one step at a time; full wavefronts
+    // instead stage K and v of two consecutive steps and d of four, written
+    // as one contiguous piece each (rows of one step are only 16 to 64 bytes).
+    constexpr int kGroup = Staged<2 * M * N>::elems + Staged<2 * N>::elems + Staged<4 * M>::elems;
+    constexpr int kStage = kGroup > Staged<M * N>::elems ? kGroup : Staged<M * N>::elems;
+    __shared__ __align__(16) OT stage[kBlock / kWave][kStage];
+    OT(*const shK)[kStage] = stage;
+    OT* const shK2w = stage[threadIdx.x / kWave];
+    OT* const shV2w = shK2w + Staged<2 * M * N>::elems;
+    OT* const shD4w = shV2w + Staged<2 * N>::elems;
     OT* const oS = (OT*)a.S;
     OT* const oV = (OT*)a.v;
     OT* const oK = (OT*)a.K;
@@ -549,9 +573,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
     }
     const uint32_t ps = a.per_step;
     const int p = a.p;
-    auto body = [&](int j, const double* rr) {
+    // A wavefront whose 64 chunks are all complete runs without per-step
+    // bounds tests (FULL); the last wavefront of the instance keeps them.
+    const bool full_wave = (cw0 + kWave <= a.NC) && ((cw0 + kWave) * B <= T) && (B % 4 == 0);
+    auto body = [&](bool FULL, int j, const double* rr) {
         const int64_t k = k0 + j;
-        if (active && k < k1) {
+        if (FULL || (active && k < k1)) {
             double F[N * N], cc[N], L[N * M], U[M * M], Js[S::size], e[N];
             if constexpr (MODE == kVar) {
                 const double* Fp = a.F + ((ps & kPS_F) ? k * N * N : 0);
@@ -584,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
                 }
             }
             double K[M * N], d[M], Ft[N * N], ct[N];
-            ok = riccati_step<N, M>(F, cc, L, U, Js, e, Sv, v, K, d, Ft, ct) && ok;
+            ok = riccati_step<N, M, HASC>(F, cc, L, U, Js, e, Sv, v, K, d, Ft, ct) && ok;
             LQT_UNROLL for (int i = 0; i < S::size; ++i) fin += Sv[i];
             LQT_UNROLL for (int i = 0; i < N; ++i) fin += v[i];
             if (wantS) {
@@ -592,9 +619,19 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
                 full_from_packed<N>(Sv, full);
                 lds_put_row<N * N>(shS[wv], lane, full);
             }
-            lds_put_row<M * N>(shK[wv], lane, K);
-            if (wantV) store_row<N>(oV + k * N, v);
-            store_row<M>(oD + k * M, d);
+            if (FULL) {
+                // slots: K and v by step parity, d by step modulo 4
+                LQT_UNROLL for (int i = 0; i < M * N; ++i)
+                    shK2w[lane * Staged<2 * M * N>::stride + (j & 1) * M * N + i] = (OT)K[i];
+                if (wantV) LQT_UNROLL for (int i = 0; i < N; ++i)
+                    shV2w[lane * Staged<2 * N>::stride + (j & 1) * N + i] = (OT)v[i];
+                LQT_UNROLL for (int i = 0; i < M; ++i)
+                    shD4w[lane * Staged<4 * M>::stride + (j & 3) * M + i] = (OT)d[i];
+            } else {
+                lds_put_row<M * N>(shK[wv], lane, K);
+                if (wantV) store_row<N>(oV + k * N, v);
+                store_row<M>(oD + k * M, d);
+            }
             // compose the chunk map: phi <- phi o (Ft, ct)
             Aff<N> step;
             LQT_UNROLL for (int i = 0; i < N * N; ++i) step.F[i] = Ft[i];
@@ -602,24 +639,49 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
             aff_after<N>(step, phi);
         }
         wave_sync();
-        if (wantS) wave_store_rows<N * N>(shS[wv], oS, cw0, a.NC, B, j, T, lane);
-        wave_store_rows<M * N>(shK[wv], oK, cw0, a.NC, B, j, T, lane);
+        if (FULL) {
+            if (wantS) wave_store_rows<N * N, false>(shS[wv], oS, cw0, a.NC, B, j, T, lane);
+            if ((j & 1) == 0) {  // steps j, j + 1 staged: rows 2 (k / 2), 2 (k / 2) + 1
+                wave_store_rows<2 * M * N, false>(shK2w, oK, cw0, a.NC, B / 2, j / 2, T / 2, lane);
+                if (wantV) wave_store_rows<2 * N, false>(shV2w, oV, cw0, a.NC, B / 2, j / 2, T / 2, lane);
+            }
+            if ((j & 3) == 0) wave_store_rows<4 * M, false>(shD4w, oD, cw0, a.NC, B / 4, j / 4, T / 4, lane);
+        } else {
+            if (wantS) wave_store_rows<N * N, true>(shS[wv], oS, cw0, a.NC, B, j, T, lane);
+            wave_store_rows<M * N, true>(shK[wv], oK, cw0, a.NC, B, j, T, lane);
+        }
         wave_sync();
     };
     // Reference rows (fast mode): step j uses rA when B-1-j is even, rB
     // otherwise; each buffer is reloaded right after use.
     double rA[N], rB[N];
-    auto fetch = [&](int j, double* buf) {
-        if constexpr (MODE == kFast) load_row<N>(a.r + clamp_row(k0 + j, k0, k1, active) * N, buf);
+    auto fetch = [&](bool FULL, int j, double* buf) {
+        if constexpr (MODE == kFast) {
+            const int64_t row = FULL ? k0 + (j < 0 ? 0 : j) : clamp_row(k0 + j, k0, k1, active);
+            load_row<N>(a.r + row * N, buf);
+        }
     };
-    fetch(B - 1, rA);
-    fetch(B - 2, rB);
-    for (int j = B - 1; j >= 0; j -= 2) {
-        body(j, rA);
-        fetch(j - 2, rA);
-        if (j - 1 >= 0) {
-            body(j - 1, rB);
-            fetch(j - 3, rB);
+    if (full_wave) {
+        fetch(true, B - 1, rA);
+        fetch(true, B - 2, rB);
+        for (int j = B - 1; j >= 0; j -= 2) {
+            body(true, j, rA);
+            fetch(true, j - 2, rA);
+            if (j - 1 >= 0) {
+                body(true, j - 1, rB);
+                fetch(true, j - 3, rB);
+            }
+        }
+    } else {
+        fetch(false, B - 1, rA);
+        fetch(false, B - 2, rB);
+        for (int j = B - 1; j >= 0; j -= 2) {
+            body(false, j, rA);
+            fetch(false, j - 2, rA);
+            if (j - 1 >= 0) {
+                body(false, j - 1, rB);
+                fetch(false, j - 3, rB);
+            }
         }
     }
     if (active) {
@@ -639,8 +701,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
 // chunk is loaded into registers before the first store.
 template <int N, int M, int BC, typename OT>
 __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
+    // full wavefronts stage x and u of four consecutive steps and write each
+    // group as one contiguous piece per chunk
+    __shared__ __align__(16) OT shX[kBlock / kWave][Staged<4 * N>::elems];
+    __shared__ __align__(16) OT shU[kBlock / kWave][Staged<4 * M>::elems];
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= a.NC) return;
+    const int64_t cw0 = c - (threadIdx.x & (kWave - 1));
+    const bool full = (cw0 + kWave <= a.NC) && ((cw0 + kWave) * BC <= a.T) && (BC % 4 == 0);
+    const int wv = threadIdx.x / kWave;
+    if (c >= a.NC) return;  // never taken in a full wavefront
     const OT* const iK = (const OT*)a.K;
     const OT* const iD = (const OT*)a.d;
     OT* const oX = (OT*)a.x;
@@ -684,7 +753,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
             LQT_UNROLL for (int q = 0; q < M; ++q) s = fma(L[i * M + q], u[q], s);
             t[i] = s;
         }
-        if (k < k1) {
+        if (full) {
+            LQT_UNROLL for (int i = 0; i < N; ++i) shX[wv][lane * Staged<4 * N>::stride + (j & 3) * N + i] = (OT)x[i];
+            LQT_UNROLL for (int q = 0; q < M; ++q) shU[wv][lane * Staged<4 * M>::stride + (j & 3) * M + q] = (OT)u[q];
+            if ((j & 3) == 3) {
+                wave_sync();
+                wave_store_rows<4 * N, false>(shX[wv], oX, cw0, a.NC, BC / 4, j / 4, T / 4, lane);
+                wave_store_rows<4 * M, false>(shU[wv], oU, cw0, a.NC, BC / 4, j / 4, T / 4, lane);
+                wave_sync();
+            }
+            LQT_UNROLL for (int i = 0; i < N; ++i) {
+                x[i] = t[i];
+                fin += t[i];
+            }
+        } else if (k < k1) {
             store_row<N>(oX + k * N, x);
             store_row<M>(oU + k * M, u);
             LQT_UNROLL for (int i = 0; i < N; ++i) {
@@ -875,8 +957,11 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     }
     {
         Stage st(h, "bwd_final", s);
-        if (all) k_bwd_final<N, M, MODE, true, OT><<<grid, kBlock, 0, s>>>(a);
-        else k_bwd_final<N, M, MODE, false, OT><<<grid, kBlock, 0, s>>>(a);
+        const bool hasc = a.c != nullptr;
+        if (all && hasc) k_bwd_final<N, M, MODE, true, OT, true><<<grid, kBlock, 0, s>>>(a);
+        else if (all) k_bwd_final<N, M, MODE, true, OT, false><<<grid, kBlock, 0, s>>>(a);
+        else if (hasc) k_bwd_final<N, M, MODE, false, OT, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bwd_final<N, M, MODE, false, OT, false><<<grid, kBlock, 0, s>>>(a);
     }
     if (a.want_fwd) {
         {
