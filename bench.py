@@ -32,6 +32,37 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 
+# Measured HBM traffic per launch of the dominant kernel (rocprofv3 --pmc
+# FETCH_SIZE, then WRITE_SIZE, on `bench.py --workload single`), scaled by the
+# plain-copy calibration (`bench.py --workload copy`: FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  Reported only while the kernel sources hash to the
+# version the counters were taken on.
+TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
+TRAFFIC = {
+    ("bwd_final", "fp64", 1_000_000): {
+        "bytes_per_launch": 346_600_000,
+        "fetch_kib": 45535.6, "write_kib": 247370.7, "fetch_scale": 2.0, "write_scale": 1.0,
+        "src_sha256": "31f3c36de2b02a785aab12e14b3095f133cb94df6eb6421d7f0236ce455d2948",
+    },
+}
+
+
+def sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_03186_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, prec, T):
+    rec = TRAFFIC.get((kernel, prec, T))
+    if rec is None or rec["src_sha256"] != sources_sha256():
+        return None
+    return rec["bytes_per_launch"]
+
 
 def algorithmic_bytes_per_step(n, m, p, osz=8):
     """Bytes a step must move by the path's contract: reference r_k read once
@@ -120,7 +151,8 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu):
     dom_bytes = stage_bytes_per_step(dom_name, n, m, prob.p, osz) * T
     achieved = dom_bytes / dom_avg_s / 1e9
     roofline = {"kernel": dom_name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom_name, prec, T),
                 "avg_us": round(dom_avg_s * 1e6, 2), "launches": dom_launches,
                 "algorithmic_bytes_per_launch": dom_bytes}
     bytes_step = algorithmic_bytes_per_step(n, m, prob.p, osz)
@@ -240,6 +272,25 @@ def run_dense(args, api, inputs, torch, prec):
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
 
 
+def run_copy(args, torch):
+    """Plain device copy of 256 MiB (float64), three times: the calibration of
+    the HBM byte counters (a copy moves exactly its size in each direction)."""
+    n = (256 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    return {"workload": "device copy of 256 MiB (counter calibration)", "bytes_each_way": n * 8,
+            "ms_per_copy": round(ms, 4), "GBps_each_way": round(n * 8 / (ms / 1e3) / 1e9, 1)}
+
+
 def run_serving(args, api, inputs, torch, prec):
     """Poisson arrivals (args.rate req/s for args.serve_seconds s), nx ~ U{4..32},
     nu = ceil(nx / 2), T log-uniform on [64, 65536], diagonal costs and
@@ -332,7 +383,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving"), default="all")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "copy"), default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--count", type=int, default=4096)
@@ -357,6 +408,9 @@ def main():
 
     if args.workload == "batched":
         print(json.dumps(run_batched(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        return
+    if args.workload == "copy":
+        print(json.dumps(run_copy(args, torch)), flush=True)
         return
     if args.workload == "dense":
         print(json.dumps(run_dense(args, api, inputs, torch, args.prec or "mixed")), flush=True)

@@ -142,9 +142,12 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_output
  * `stream`, synchronous) with several chunk lengths for every launch group
  * (size class 8, 16, 32, 64 x wavefront / workgroup engine) present, and
  * keeps the fastest for later solves of this plan: the chunk length of an
- * instance is about T / div steps (16 <= length <= 256) with div in
- * {16, 32, 64, 128, 256} (default 64).  chosen (may be NULL) receives the
- * div of the 8 groups (index 2 * class_index + engine).  The chunking changes
+ * instance becomes about T / div steps (at least 16) with div in
+ * {1, 4, 16, 64, 256}; div = 1 solves every instance of the group as one
+ * chunk (sequential down-sweep, no element fold), which pays when the batch
+ * alone fills the GPU.  Untuned groups keep the default (about 64 chunks of
+ * 16 to 256 steps).  chosen (may be NULL) receives the div of the 8 groups
+ * (index 2 * class_index + engine; 0 = default).  The chunking changes
  * the association order of the scan, so results of a tuned plan differ from
  * an untuned one by rounding only; within a plan a result never depends on
  * the batch it is solved in. */

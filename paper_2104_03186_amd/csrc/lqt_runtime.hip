@@ -65,19 +65,25 @@ int eng_of(const lqt_problem& p) {
     return 0;
 }
 
-// Chunk length of a chunked-path instance: about `div` chunks per instance
-// (default 64; lqt_tune picks div per launch group), between 16 and 256
-// steps.  LQT_WCHUNK fixes the length (tests).
-constexpr int kDefaultDiv = 64;
-constexpr int kTuneDivs[] = {16, 32, 64, 128, 256};
+// Chunk length of a chunked-path instance.  Default: about 64 chunks per
+// instance, between 16 and 256 steps.  A plan tuned by lqt_tune uses about
+// `div` chunks per instance for the launch group, at least 16 steps each
+// (div = 1: one chunk, no element fold at all -- the instance is then solved
+// by the sequential down-sweep alone, which pays when a batch has enough
+// instances to fill the GPU).  LQT_WCHUNK fixes the length (tests).
+constexpr int kTuneDivs[] = {1, 4, 16, 64, 256};
 
-int wave_chunk(int64_t T, int div = kDefaultDiv) {
+int wave_chunk(int64_t T, int div = 0) {
     if (const char* e = getenv("LQT_WCHUNK")) {
         int b = atoi(e);
         if (b >= 1 && b <= 4096) return b;
     }
-    int64_t b = (T + div - 1) / div;
-    return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
+    if (div <= 0) {
+        const int64_t b = (T + 63) / 64;
+        return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
+    }
+    const int64_t b = (T + div - 1) / div;
+    return (int)std::max<int64_t>(16, std::min<int64_t>(int64_t(1) << 30, b));
 }
 
 // Launch group of a chunked-path instance: size class (8, 16, 32, 64) and
@@ -243,8 +249,7 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
 }
 
 int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
-    const int d = plan ? plan->tune_div[group_key(p)] : 0;
-    return wave_chunk(p.T, d > 0 ? d : kDefaultDiv);
+    return wave_chunk(p.T, plan ? plan->tune_div[group_key(p)] : 0);
 }
 
 // Workspace of one wavefront-path instance, and of its K, d scratch when the
@@ -720,7 +725,7 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
             }
         if (ps.empty()) continue;
         float best = 0.f;
-        int best_div = kDefaultDiv;
+        int best_div = 0;
         for (int div : kTuneDivs) {
             plan->tune_div[key] = div;
             float ms = 0.f;
@@ -743,7 +748,7 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (chosen)
-        for (int key = 0; key < 8; ++key) chosen[key] = plan->tune_div[key] > 0 ? plan->tune_div[key] : kDefaultDiv;
+        for (int key = 0; key < 8; ++key) chosen[key] = plan->tune_div[key];
     return st;
 }
 

@@ -681,6 +681,9 @@ __global__ __launch_bounds__(kW) void t_fold(const GInst* inst, int ninst, int64
     if (gc >= nchunks) return;
     const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
+    // the first chunk's element is never used: the chain needs the elements
+    // of chunks 1..NC-1 only (the value at the start of chunk 0 is not an input)
+    if (c == 0) return;
     const int lane = threadIdx.x;
     const int n = I.n, m = I.m, p = I.p;
     TSlots<N> s = tslots<N>(dyn);
@@ -759,7 +762,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     tstore<N>(n, n, Sm, vo, n, lane);
     if (lane < n) vo[nn + lane] = v[lane];
 #pragma unroll 1
-    for (int64_t c = I.NC - 1; c >= 0; --c) {
+    for (int64_t c = I.NC - 1; c >= 1; --c) {  // val[0] is never read
         const double* e = ws.agg + c * elem_doubles(n);
         tload<N>(n, n, e, n, EA, lane);
         tload<N>(n, n, e + nn + n, n, EC, lane);
