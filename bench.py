@@ -40,9 +40,9 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
 TRAFFIC = {
     ("bwd_final", "fp64", 1_000_000): {
-        "bytes_per_launch": 346_600_000,
-        "fetch_kib": 45535.6, "write_kib": 247370.7, "fetch_scale": 2.0, "write_scale": 1.0,
-        "src_sha256": "31f3c36de2b02a785aab12e14b3095f133cb94df6eb6421d7f0236ce455d2948",
+        "bytes_per_launch": 342_657_229,
+        "fetch_kib": 43228.7, "write_kib": 248168.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "src_sha256": "261f728bc524daca0f1e2fef990cb4f02474c3b2a866da8c11856a121c39ffbd",
     },
 }
 

@@ -9,6 +9,9 @@ namespace lqt {
 enum : uint32_t { kPS_F = 1, kPS_c = 2, kPS_L = 4, kPS_H = 8, kPS_X = 16, kPS_U = 32 };
 
 // Kernel arguments of the lane-per-element pipeline for one instance.
+// Wavefront units per block in the backward top levels of the lane pipeline.
+constexpr int kSmallTopBlock = 256;
+
 struct SmallArgs {
     // problem (device pointers)
     const double *F, *c, *L, *U, *H, *X, *r, *HT, *XT, *rT, *x0;
@@ -27,9 +30,12 @@ struct SmallArgs {
     double* wave_val;  // [NG + 1] value function at wavefront-unit starts
     double* lane_aff;  // [NC] in-wave prefix affine maps
     double* wave_x;    // [NG] state at wavefront-unit starts
+    double* mid_el;    // [NG] in-block suffixes of the unit totals (NG > kSmallTopBlock)
+    double* blk_val;   // [NB + 1] value function at block starts (NG > kSmallTopBlock)
     int64_t NC;        // number of chunks
     int32_t B;         // steps per chunk
     int32_t NG;        // number of wavefront units (64 chunks each)
+    int32_t NB;        // blocks of kSmallTopBlock units
     int32_t want_fwd;  // run the forward pass
 };
 

@@ -217,9 +217,9 @@ int chunk_length(int64_t T) {
 }
 
 struct Layout {
-    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, K, d, total;
+    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, total;
     int64_t NC;
-    int B, NG;
+    int B, NG, NB;
 };
 
 Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
@@ -229,6 +229,8 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
     L.B = chunk_length(p.T);
     L.NC = (p.T + L.B - 1) / L.B;
     L.NG = (int)((L.NC + 63) / 64);
+    L.NB = (L.NG + lqt::kSmallTopBlock - 1) / lqt::kSmallTopBlock;
+    const bool blocks = L.NG > lqt::kSmallTopBlock;
     const bool var = p.per_step != 0;
     size_t off = 0;
     auto take = [&](size_t doubles) {
@@ -242,6 +244,8 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
     L.wave_val = take((size_t)(L.NG + 1) * small_val_doubles(n));
     L.lane_aff = take((size_t)L.NC * small_aff_doubles(n));
     L.wave_x = take((size_t)L.NG * n);
+    L.mid_el = take(blocks ? (size_t)L.NG * small_elem_doubles(n) : 0);
+    L.blk_val = take(blocks ? (size_t)(L.NB + 1) * small_val_doubles(n) : 0);
     L.K = take(need_K ? (size_t)p.T * m * n : 0);
     L.d = take(need_d ? (size_t)p.T * m : 0);
     L.total = off;
@@ -364,7 +368,9 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.wave_val = (double*)(base + L.wave_val);
     a.lane_aff = (double*)(base + L.lane_aff);
     a.wave_x = (double*)(base + L.wave_x);
-    a.NC = L.NC; a.B = L.B; a.NG = L.NG;
+    a.mid_el = (double*)(base + L.mid_el);
+    a.blk_val = (double*)(base + L.blk_val);
+    a.NC = L.NC; a.B = L.B; a.NG = L.NG; a.NB = L.NB;
     a.want_fwd = fwd ? 1 : 0;
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr);

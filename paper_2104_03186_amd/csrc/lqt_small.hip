@@ -32,6 +32,7 @@ namespace lqt {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+static_assert(kBlock == kSmallTopBlock, "blocks of wavefront units in the backward top levels");
 
 // Orders this wavefront's LDS accesses around a cooperative transfer.  Each
 // staging area belongs to one wavefront, whose LDS operations execute in
@@ -435,63 +436,154 @@ __global__ __launch_bounds__(kBlock) void k_bwd_reduce(SmallArgs a) {
     if (active) store_elem<N>(a.lane_el + c * Elem<N>::size, P);
 }
 
-// One workgroup: the value function at the first step of every wavefront
-// unit g (stored in wave_val[g]), from the unit totals (= the in-wave suffix
-// of each unit's first lane) and the terminal value.
+// Suffix scan across the wavefronts of a workgroup.  On entry lane 0 of
+// wavefront wv holds that wavefront's total in `agg`; nw wavefronts hold
+// elements.
+// On return R holds the suffix of the totals of wavefronts wv+1 .. nw-1
+// (has_R false: there is none).  Hillis-Steele over the nw totals, ping-pong
+// buffers in LDS, one workgroup barrier per round (nw is uniform).
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_bwd_top(SmallArgs a, int64_t ld_cst_st) {
+LQT_DI bool wave_suffix(double (*sh)[kBlock / kWave][Elem<N>::size], const Elem<N>& agg, int nw, Elem<N>& R) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    if (lane == 0) store_elem<N>(sh[0][wv], agg);
+    __syncthreads();
+    int src = 0;
+    if (nw > 2) {
+        Elem<N> X;
+        load_elem<N>(sh[0][wv], X);
+        for (int d = 1; d < nw; d <<= 1) {
+            if (wv + d < nw) {
+                Elem<N> Y;
+                load_elem<N>(sh[src][wv + d], Y);
+                combine<N>(X, Y);
+                X = Y;
+            }
+            if (lane == 0) store_elem<N>(sh[src ^ 1][wv], X);
+            __syncthreads();
+            src ^= 1;
+        }
+    }
+    const bool has_R = wv + 1 < nw;
+    if (has_R) load_elem<N>(sh[src][wv + 1], R);
+    return has_R;
+}
+
+// One workgroup: reverse scan of cnt elements el[g * stride], g = 0..cnt-1
+// (each covering a run of consecutive steps, in time order), anchored on the
+// value term (packed S, then v): out[g] = value function at the first step
+// covered by element g, out[cnt] = term.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_bwd_top(const double* el, int64_t stride, int cnt, const double* term,
+                                                    double* out) {
     using S = Sym<N>;
     constexpr int VS = S::size + N;
-    __shared__ double sh[kBlock / kWave][Elem<N>::size];
+    __shared__ double sh[2][kBlock / kWave][Elem<N>::size];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int wv = tid / kWave;
-    const int NG = a.NG;
-    const int q = (NG + kBlock - 1) / kBlock;
-    const int lo = tid * q < NG ? tid * q : NG;
-    const int hi = lo + q < NG ? lo + q : NG;
+    const int q = (cnt + kBlock - 1) / kBlock;
+    const int lo = tid * q < cnt ? tid * q : cnt;
+    const int hi = lo + q < cnt ? lo + q : cnt;
+    const int nt = (cnt + q - 1) / q;                         // threads holding elements
+    const int nw = (nt + kWave - 1) / kWave;                  // wavefronts holding elements
     Elem<N> agg, tot;
-    set_identity<N>(agg);
-    for (int g = hi - 1; g >= lo; --g) {
-        load_elem<N>(a.lane_el + (int64_t)g * kWave * Elem<N>::size, tot);
-        combine<N>(tot, agg);
+    if (hi > lo) {
+        load_elem<N>(el + (int64_t)(hi - 1) * stride, agg);
+        for (int g = hi - 2; g >= lo; --g) {
+            load_elem<N>(el + (int64_t)g * stride, tot);
+            combine<N>(tot, agg);
+        }
+    } else {
+        set_identity<N>(agg);
     }
-    // reverse inclusive scan of agg across the block
-    for (int d = 1; d < kWave; d <<= 1) {
+    // suffix across the wavefront (rounds beyond the populated lanes skipped)
+    for (int d = 1; d < kWave && d < nt; d <<= 1) {
         Elem<N> Q = shfl_down_elem<N>(agg, d);
-        if (lane + d < kWave) {
+        if (lane + d < kWave && tid + d < nt) {
             combine<N>(agg, Q);
             agg = Q;
         }
     }
-    if (lane == 0) store_elem<N>(sh[wv], agg);
-    __syncthreads();
     Elem<N> R;
-    set_identity<N>(R);
-    for (int w = kBlock / kWave - 1; w > wv; --w) {
-        load_elem<N>(sh[w], tot);
-        combine<N>(tot, R);
-    }
-    // suffix strictly after this lane, then anchored on the terminal value
+    const bool has_R = wave_suffix<N>(sh, agg, nw, R);
+    // suffix strictly after this thread's range, then anchored on the terminal value
     Elem<N> nxt = shfl_down_elem<N>(agg, 1);
-    if (lane == kWave - 1) set_identity<N>(nxt);
-    combine<N>(nxt, R);
+    const bool has_nxt = lane + 1 < kWave && tid + 1 < nt;
+    if (has_R) {
+        if (has_nxt) combine<N>(nxt, R);
+        nxt = R;
+    }
     double Sv[S::size], v[N];
-    LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = a.cst[ld_cst_st + i];
-    LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = a.cst[ld_cst_st + S::size + i];
-    anchor<N>(R, Sv, v);
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = term[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = term[S::size + i];
+    if (has_R || has_nxt) anchor<N>(nxt, Sv, v);
     for (int g = hi - 1; g >= lo; --g) {
-        load_elem<N>(a.lane_el + (int64_t)g * kWave * Elem<N>::size, tot);
+        load_elem<N>(el + (int64_t)g * stride, tot);
         anchor<N>(tot, Sv, v);
-        double* o = a.wave_val + (int64_t)g * VS;
+        double* o = out + (int64_t)g * VS;
         LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = Sv[i];
         LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = v[i];
     }
     if (tid == 0) {
-        double* o = a.wave_val + (int64_t)NG * VS;
-        LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = a.cst[ld_cst_st + i];
-        LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = a.cst[ld_cst_st + S::size + i];
+        double* o = out + (int64_t)cnt * VS;
+        LQT_UNROLL for (int i = 0; i < VS; ++i) o[i] = term[i];
     }
+}
+
+// Long instances (more than kBlock wavefront units): the units are grouped
+// in blocks of kBlock, one workgroup each.  mid_el[g] = E_g (x) ... (x) E_l,
+// E_g the total of unit g (the in-wave suffix of its first lane) and l the
+// last unit of g's block; the first unit's entry is the block total.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_bwd_mid(SmallArgs a) {
+    __shared__ double sh[2][kBlock / kWave][Elem<N>::size];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g = g0 + tid;
+    const int nb = (int)(a.NG - g0 < kBlock ? a.NG - g0 : kBlock);  // units in this block
+    const int nw = (nb + kWave - 1) / kWave;
+    Elem<N> agg;
+    if (tid < nb) load_elem<N>(a.lane_el + g * kWave * Elem<N>::size, agg);
+    else set_identity<N>(agg);
+    for (int d = 1; d < kWave; d <<= 1) {
+        Elem<N> Q = shfl_down_elem<N>(agg, d);
+        if (lane + d < kWave && tid + d < nb) {
+            combine<N>(agg, Q);
+            agg = Q;
+        }
+    }
+    Elem<N> R;
+    if (wave_suffix<N>(sh, agg, nw, R)) {
+        combine<N>(agg, R);
+        agg = R;
+    }
+    if (tid < nb) store_elem<N>(a.mid_el + g * Elem<N>::size, agg);
+}
+
+// wave_val[g] = mid_el[g] anchored on the value at the start of the next
+// block (blk_val, from k_bwd_top over the block totals); wave_val[NG] = the
+// terminal value.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_bwd_down(SmallArgs a, int64_t ld_cst_st) {
+    using S = Sym<N>;
+    constexpr int VS = S::size + N;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g > a.NG) return;
+    double* o = a.wave_val + g * VS;
+    if (g == a.NG) {
+        LQT_UNROLL for (int i = 0; i < VS; ++i) o[i] = a.cst[ld_cst_st + i];
+        return;
+    }
+    const double* bv = a.blk_val + (g / kBlock + 1) * VS;
+    double Sv[S::size], v[N];
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = bv[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = bv[S::size + i];
+    Elem<N> e;
+    load_elem<N>(a.mid_el + g * Elem<N>::size, e);
+    anchor<N>(e, Sv, v);
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = Sv[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = v[i];
 }
 
 // Per-block copy of the time-invariant step data (read from LDS inside the
@@ -781,7 +873,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final_regs(SmallArgs a) {
 
 // ---- forward pass ----------------------------------------------------------
 
-// One workgroup: the state at the first step of every wavefront unit.
+// One workgroup: the state at the first step of every wavefront unit.  Up
+// to kFwdRegs unit totals per thread are loaded once, all at the start, and
+// kept in registers for the roll-out at the end.
+constexpr int kFwdRegs = 4;
+
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
     __shared__ double sh[kBlock / kWave][Aff<N>::size];
@@ -797,12 +893,29 @@ __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
         const int64_t last = (first + kWave < a.NC ? first + kWave : a.NC) - 1;
         load_aff<N>(a.lane_aff + last * Aff<N>::size, t);
     };
+    const bool regs = q <= kFwdRegs;
+    Aff<N> u[kFwdRegs];
+    if (regs) {
+        LQT_UNROLL for (int i = 0; i < kFwdRegs; ++i) {
+            if (lo + i < hi) unit_total(lo + i, u[i]);
+        }
+    }
     Aff<N> agg, t;
     aff_identity<N>(agg);
-    for (int g = lo; g < hi; ++g) {
-        unit_total(g, t);
-        aff_after<N>(agg, t);
-        agg = t;
+    if (regs) {
+        LQT_UNROLL for (int i = 0; i < kFwdRegs; ++i) {
+            if (lo + i < hi) {
+                t = u[i];
+                aff_after<N>(agg, t);
+                agg = t;
+            }
+        }
+    } else {
+        for (int g = lo; g < hi; ++g) {
+            unit_total(g, t);
+            aff_after<N>(agg, t);
+            agg = t;
+        }
     }
     for (int d = 1; d < kWave; d <<= 1) {
         Aff<N> Q = shfl_up_aff<N>(agg, d);
@@ -824,11 +937,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
     LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = a.x0[i];
     mv<N, N>(prev.F, x, nx);
     LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + prev.c[i];
-    for (int g = lo; g < hi; ++g) {
-        LQT_UNROLL for (int i = 0; i < N; ++i) a.wave_x[(int64_t)g * N + i] = x[i];
-        unit_total(g, t);
-        mv<N, N>(t.F, x, nx);
-        LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + t.c[i];
+    if (regs) {
+        LQT_UNROLL for (int k = 0; k < kFwdRegs; ++k) {
+            if (lo + k < hi) {
+                LQT_UNROLL for (int i = 0; i < N; ++i) a.wave_x[(int64_t)(lo + k) * N + i] = x[i];
+                mv<N, N>(u[k].F, x, nx);
+                LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + u[k].c[i];
+            }
+        }
+    } else {
+        for (int g = lo; g < hi; ++g) {
+            LQT_UNROLL for (int i = 0; i < N; ++i) a.wave_x[(int64_t)g * N + i] = x[i];
+            unit_total(g, t);
+            mv<N, N>(t.F, x, nx);
+            LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + t.c[i];
+        }
     }
 }
 
@@ -951,9 +1074,22 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         Stage st(h, "bwd_reduce", s);
         k_bwd_reduce<N, M, MODE><<<grid, kBlock, 0, s>>>(a);
     }
-    {
+    if (a.NG > kBlock) {
+        {
+            Stage st(h, "bwd_mid", s);
+            k_bwd_mid<N><<<(unsigned)a.NB, kBlock, 0, s>>>(a);
+        }
+        {
+            Stage st(h, "bwd_top", s);
+            k_bwd_top<N><<<1, kBlock, 0, s>>>(a.mid_el, (int64_t)kBlock * Elem<N>::size, a.NB, a.cst + CL::ST,
+                                               a.blk_val);
+        }
+        Stage st(h, "bwd_down", s);
+        k_bwd_down<N><<<(unsigned)((a.NG + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, CL::ST);
+    } else {
         Stage st(h, "bwd_top", s);
-        k_bwd_top<N><<<1, kBlock, 0, s>>>(a, CL::ST);
+        k_bwd_top<N><<<1, kBlock, 0, s>>>(a.lane_el, (int64_t)kWave * Elem<N>::size, a.NG, a.cst + CL::ST,
+                                           a.wave_val);
     }
     {
         Stage st(h, "bwd_final", s);

@@ -99,6 +99,20 @@ def test_tracking_chunk_sizes(api, plan, T, chunk):
 DIMS = [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (3, 3), (4, 1), (4, 2), (4, 3), (4, 4)]
 
 
+@pytest.mark.parametrize("T,chunk", [(16384, 1), (16385, 1), (16448, 1), (32769, 1), (49152, 1), (2_000_000, 2),
+                                     (4_195_304, 1)])
+def test_top_level_blocks(api, plan, T, chunk):
+    """Wavefront-unit counts (64 chunks each) around the 256-unit blocks of
+    the backward top levels: exactly one block, one unit more, several blocks
+    with a ragged last one, and more than 256 blocks (several block totals per
+    thread of the top scan)."""
+    _say("tracking n=4 m=2 T=", T, "chunk=", chunk, "units=", -(-(-(-T // chunk)) // 64))
+    prob = inputs.tracking_problem(n=4, m=2, T=T, instance=2)
+    do = solve(api, plan, prob, chunk=chunk)
+    assert int(do.status.item()) == 0
+    assert_parity(do.host(), oracle.solve(prob))
+
+
 @pytest.mark.parametrize("per_step", [0, 1 | 2 | 4 | 8 | 16 | 32, 1 | 8])
 @pytest.mark.parametrize("nm", DIMS)
 def test_random_problems(api, plan, nm, per_step):
