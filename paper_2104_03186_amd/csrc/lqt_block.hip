@@ -39,38 +39,41 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 namespace blk64 {
 constexpr int N = 64, M = 32, NW = 4;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[6] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll"};
+constexpr const char* kNames[8] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll",
+                                    "t64_fmat", "t64_fvec"};
 #include "lqt_block.inc"
 }  // namespace blk64
 
 namespace blk32 {
 constexpr int N = 32, M = 32, NW = 2;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[6] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll"};
+constexpr const char* kNames[8] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll",
+                                    "b32_fmat", "b32_fvec"};
 #include "lqt_block.inc"
 }  // namespace blk32
 
 namespace blk16 {
 constexpr int N = 16, M = 16, NW = 1;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[6] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll"};
+constexpr const char* kNames[8] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll",
+                                    "b16_fmat", "b16_fvec"};
 #include "lqt_block.inc"
 }  // namespace blk16
 
-hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
-                       hipStream_t s, const StageHook* h) {
+hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
+                       bool f32, hipStream_t s, const StageHook* h) {
     switch (N) {
         case 64:
-            if (f32) blk64::run_block<float>(d_inst, ninst, nchunks, want_fwd, s, h);
-            else blk64::run_block<double>(d_inst, ninst, nchunks, want_fwd, s, h);
+            if (f32) blk64::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            else blk64::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
             break;
         case 32:
-            if (f32) blk32::run_block<float>(d_inst, ninst, nchunks, want_fwd, s, h);
-            else blk32::run_block<double>(d_inst, ninst, nchunks, want_fwd, s, h);
+            if (f32) blk32::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            else blk32::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
             break;
         case 16:
-            if (f32) blk16::run_block<float>(d_inst, ninst, nchunks, want_fwd, s, h);
-            else blk16::run_block<double>(d_inst, ninst, nchunks, want_fwd, s, h);
+            if (f32) blk16::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            else blk16::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
             break;
         default:
             return hipErrorInvalidValue;

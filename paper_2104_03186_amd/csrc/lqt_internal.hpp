@@ -72,8 +72,8 @@ hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bo
                       hipStream_t s, const StageHook* h);
 // Workgroup engines (N = 16, 32, 64; time-invariant except c; class 64:
 // n, p, pT <= 64 and m <= 32).
-hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
-                       hipStream_t s, const StageHook* h);
+hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
+                       bool f32, hipStream_t s, const StageHook* h);
 
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);

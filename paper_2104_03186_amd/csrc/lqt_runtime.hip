@@ -261,7 +261,7 @@ int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
 size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
     const int B = chunk_for(plan, p);
     const int64_t NC = (p.T + B - 1) / B;
-    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(p), NC) * sizeof(double));
+    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(p), NC, B, p.c != nullptr) * sizeof(double));
 }
 size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
     return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
@@ -454,17 +454,18 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     for (size_t j0 = 0; j0 < wave.size();) {
         size_t j1 = j0;
-        int64_t nch = 0;
+        int64_t nch = 0, max_nc = 0;
         bool fwd = false;
         while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
             nch += A.ginst_host[j1].NC;
+            max_nc = std::max(max_nc, A.ginst_host[j1].NC);
             fwd = fwd || want_fwd_c[j1];
             ++j1;
         }
         const lqt_problem& p0 = probs[wave[j0]];
         const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
         const int eng = eng_of(p0);
-        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
+        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, f32, s,
                                               plan->prof.on ? &hook : nullptr)
                            : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
                                              plan->prof.on ? &hook : nullptr);
@@ -674,7 +675,7 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
             const int64_t NC = (desc->max_steps + B - 1) / B;
             const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
             const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC),
-                                        lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC));
+                                        lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC, B, false));
             const size_t w = (size_t)wd * 8 +
                              (size_t)desc->max_steps * (desc->max_nu * desc->max_nx + desc->max_nu) * 8 + 4096;
             need = std::max(need, w);

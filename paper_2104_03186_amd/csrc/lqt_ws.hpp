@@ -77,16 +77,30 @@ __host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int eng) 
     return (e + 31) & ~int64_t(31);
 }
 
-// cst | agg[NC] (chunk elements) | val[NC + 1] (value at chunk starts and T)
-//     | map[NC] (chunk affine maps) | xs[NC] (state at chunk starts)
-__host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int64_t NC) {
+// Operator form of the chunk fold (workgroup engines, instances without
+// offsets c): every chunk after the first has the full length B and, the
+// instance being time-invariant, the same matrix part (A, C, J); its vector
+// part (b, eta) is linear in the chunk's references.  ops holds, for the
+// relative steps j = 1 .. B-1 of the fold, the two d x d operators that carry
+// eta_P into the new (eta, b); opr the 2d x (B p) matrix that maps the chunk's
+// references (time order, p per step) to its (b, eta).
+__host__ __device__ inline bool ws_op_form(int eng, bool has_c) { return eng != 0 && !has_c; }
+__host__ __device__ inline int64_t ws_ops_doubles(int d, int64_t B) { return (B > 1 ? B - 1 : 0) * 2 * (int64_t)d * d; }
+__host__ __device__ inline int64_t ws_opr_doubles(int d, int64_t B, int p) { return 2 * (int64_t)d * B * p; }
+
+// cst | agg[NC] (chunk elements; in the operator form agg[0] holds the common
+//     matrix part) | val[NC + 1] (value at chunk starts and T) | map[NC] (chunk
+//     affine maps) | xs[NC] (state at chunk starts) | ops | opr (operator form)
+__host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int64_t NC, int64_t B = 0,
+                                              bool has_c = true) {
     const int d = ws_dim(n, eng);
+    const int64_t ops = ws_op_form(eng, has_c) ? ws_ops_doubles(d, B) + ws_opr_doubles(d, B, p) : 0;
     return ws_cst_doubles(n, m, p, eng) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
-           NC * d + 32;
+           NC * d + ops + 32;
 }
 
 struct InstWs {
-    double *cst, *agg, *val, *map, *xs;
+    double *cst, *agg, *val, *map, *xs, *ops, *opr;
     int d;  // record dimension
 };
 
@@ -99,6 +113,8 @@ __device__ inline InstWs inst_ws(const GInst& I) {
     w.val = w.agg + I.NC * elem_doubles(d);
     w.map = w.val + (I.NC + 1) * val_doubles(d);
     w.xs = w.map + I.NC * val_doubles(d);
+    w.ops = w.xs + I.NC * d;
+    w.opr = w.ops + ws_ops_doubles(d, I.B);
     return w;
 }
 
