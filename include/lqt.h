@@ -59,7 +59,7 @@ typedef enum {
     LQT_EAGAIN = 5,      /* lqt_poll: the request has not completed yet            */
     LQT_EBUSY = 6,       /* lqt_submit: the in-flight queue is full                */
     LQT_EHIP = 7,        /* a HIP runtime call failed                              */
-    LQT_ENOTSUP = 8      /* a dimension or precision this build does not provide   */
+    LQT_ENOTSUP = 8      /* a dimension or precision the library does not provide */
 } lqt_status;
 
 typedef enum {

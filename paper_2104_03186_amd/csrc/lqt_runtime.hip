@@ -22,7 +22,7 @@
 
 namespace {
 
-constexpr int kMaxNx = 64;         // largest state dimension of this build's kernels
+constexpr int kMaxNx = 64;         // largest state dimension of the kernels
 constexpr int kWaveMaxN = 64;      // chunked paths: n, p, pT up to this (m up to 32 above 32)
 constexpr int64_t kSmallMinT = 8192;  // lane-per-element path for long n <= 4 instances
 
@@ -642,7 +642,7 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     if (desc->max_nx < 1 || desc->max_nu < 1)
         return fail(nullptr, LQT_EINVAL, "lqt_plan: max_nx and max_nu must be >= 1");
     if (desc->max_nx > kMaxNx)
-        return fail(nullptr, LQT_ENOTSUP, "lqt_plan: max_nx=%d exceeds this build's limit %d", desc->max_nx, kMaxNx);
+        return fail(nullptr, LQT_ENOTSUP, "lqt_plan: max_nx=%d exceeds the library's limit %d", desc->max_nx, kMaxNx);
     if (desc->prec != LQT_PREC_FP64 && desc->prec != LQT_PREC_MIXED)
         return fail(nullptr, LQT_EINVAL, "lqt_plan: unknown precision %d", (int)desc->prec);
     int ndev = 0;
