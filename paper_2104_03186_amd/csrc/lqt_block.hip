@@ -1,6 +1,6 @@
 // Workgroup-per-chunk LQT pipeline (gfx950) for time-invariant instances of
-// the classes 16 and 32 and for the dense class 32 < max(n, m, p, pT) <= 64,
-// m <= 32.
+// the classes 16 and 32 (class 32 in two variants: 32- or 16-wide control
+// blocks) and for the dense class 32 < max(n, m, p, pT) <= 64, m <= 32.
 //
 // One workgroup owns one chunk of B consecutive steps (class 64: four
 // wavefronts, 64 x 64 zero-padded state, about 155 KB of the 160 KB of LDS;
@@ -52,6 +52,14 @@ constexpr const char* kNames[8] = {"b32_prep", "b32_fold", "b32_chain", "b32_fin
 #include "lqt_block.inc"
 }  // namespace blk32
 
+namespace blk32h {
+constexpr int N = 32, M = 16, NW = 2;
+using CB = CstBT<N, M>;
+constexpr const char* kNames[8] = {"b32h_prep", "b32h_fold", "b32h_chain", "b32h_final", "b32h_fchain", "b32h_roll",
+                                   "b32h_fmat", "b32h_fvec"};
+#include "lqt_block.inc"
+}  // namespace blk32h
+
 namespace blk16 {
 constexpr int N = 16, M = 16, NW = 1;
 using CB = CstBT<N, M>;
@@ -70,6 +78,10 @@ hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, i
         case 32:
             if (f32) blk32::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
             else blk32::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            break;
+        case kEng32m16:
+            if (f32) blk32h::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            else blk32h::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
             break;
         case 16:
             if (f32) blk16::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);

@@ -61,7 +61,8 @@ int eng_of(const lqt_problem& p) {
     if (cls == 64) return 64;
     const char* e = getenv("LQT_BLOCK");
     const bool allow = !(e && !strcmp(e, "0"));
-    if (allow && (cls == 16 || cls == 32) && !(p.per_step & ~(uint32_t)LQT_PS_c)) return cls;
+    if (allow && (cls == 16 || cls == 32) && !(p.per_step & ~(uint32_t)LQT_PS_c))
+        return (cls == 32 && p.nu <= 16) ? lqt::kEng32m16 : cls;
     return 0;
 }
 
@@ -386,7 +387,10 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     std::vector<int> small, wave;
     for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
     // launch groups: (size class, engine)
-    auto cls = [&](int i) { return 2 * tile_class_of(probs[i]) + (eng_of(probs[i]) ? 1 : 0); };
+    auto cls = [&](int i) {
+        const int e = eng_of(probs[i]);
+        return 4 * tile_class_of(probs[i]) + (e == 0 ? 0 : (e == lqt::kEng32m16 ? 2 : 1));
+    };
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
     // workspace: [small-path region (largest small instance)] [wave region] [instance table]
     BatchSize bs(plan);

@@ -55,11 +55,17 @@ struct CstBT {
 };
 
 // Engine of an instance: 0 = wavefront engine (records of dimension n), or
-// the padded state dimension (16, 32, 64) of a workgroup engine.
+// a workgroup engine: 16, 32, 64 (padded state dimension N, control blocks
+// M = min(N, 32)) or kEng32m16 (N = 32 with M = 16, for m <= 16).
+constexpr int kEng32m16 = 33;
+
+__host__ __device__ inline int eng_dim(int eng) { return eng == kEng32m16 ? 32 : eng; }
+
 __host__ __device__ inline int64_t eng_cst_end(int eng) {
     switch (eng) {
         case 16: return CstBT<16, 16>::end;
         case 32: return CstBT<32, 32>::end;
+        case kEng32m16: return CstBT<32, 16>::end;
         case 64: return CstBT<64, 32>::end;
     }
     return 0;
@@ -71,7 +77,7 @@ __host__ __device__ inline int64_t elem_doubles(int n) { return 3 * (int64_t)n *
 __host__ __device__ inline int64_t val_doubles(int n) { return (int64_t)n * n + n; }
 
 // Record dimension and constants size of an instance on engine `eng`.
-__host__ __device__ inline int ws_dim(int n, int eng) { return eng ? eng : n; }
+__host__ __device__ inline int ws_dim(int n, int eng) { return eng ? eng_dim(eng) : n; }
 __host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int eng) {
     const int64_t e = eng ? eng_cst_end(eng) : cst_layout(n, m, p > 0 ? p : 1).end;
     return (e + 31) & ~int64_t(31);

@@ -99,6 +99,17 @@ def test_padding_shapes(api, plans, prec, nm):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("T,chunk", [(130, 16), (257, 128), (64, 1)])
+def test_operator_form_padding(api, plans, prec, T, chunk):
+    # no offsets (operator-form fold) with padding: n = 40, m = 20, p = 33
+    prob = inputs.random_problem(40, 20, T, seed=T + chunk, p=33, pT=40, with_c=False, scale=0.95)
+    _say("operator form n=40 m=20 p=33 T=", T, "chunk=", chunk, prec)
+    do = run(api, plans[prec], [prob], prec, chunk=chunk)[0]
+    assert int(do.status.item()) == 0
+    check(do.host(), oracle.solve(prob), TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_per_step_offsets(api, plans, prec):
     prob = inputs.random_problem(40, 12, 200, seed=77, p=40, pT=40, per_step=2, scale=0.95)
     _say("per-step c, n=40", prec)

@@ -79,7 +79,7 @@ def check(got: dict, ref: dict, tol=TOL):
 
 
 NM = [(1, 1), (2, 1), (3, 2), (4, 2), (5, 2), (5, 5), (6, 3), (8, 4), (8, 1), (12, 6), (16, 8), (16, 16),
-      (24, 12), (32, 16), (7, 9)]
+      (24, 12), (32, 16), (7, 9), (20, 18), (32, 32)]
 
 
 @pytest.mark.parametrize("nm", NM)
@@ -91,6 +91,22 @@ def test_random_dims(api, plan, nm):
         do = run(api, plan, [prob], chunk=chunk)[0]
         assert int(do.status.item()) == 0
         check(do.host(), oracle.solve(prob))
+
+
+@pytest.mark.parametrize("nm,T,chunk", [((12, 5), 300, None), ((16, 16), 257, 16), ((24, 12), 1000, None),
+                                        ((32, 16), 333, 32), ((17, 3), 64, 1), ((20, 18), 129, 16),
+                                        ((32, 32), 200, None), ((30, 9), 47, 64)])
+def test_operator_form(api, plan, nm, T, chunk):
+    """Instances without offsets: on the workgroup engines the chunk fold runs
+    in operator form (matrix fold once per instance, vector part as a GEMM);
+    classes 16, 32 (16- and 32-wide control blocks), ragged first chunks,
+    one-step chunks, a chunk longer than the horizon."""
+    n, m = nm
+    _say("operator form n=", n, "m=", m, "T=", T, "chunk=", chunk)
+    prob = inputs.random_problem(n, m, T, seed=31 * n + m + T, p=max(1, n - 2), pT=n, with_c=False, scale=0.95)
+    do = run(api, plan, [prob], chunk=chunk)[0]
+    assert int(do.status.item()) == 0
+    check(do.host(), oracle.solve(prob))
 
 
 @pytest.mark.parametrize("per_step", [1 | 2 | 4 | 8 | 16 | 32, 4 | 32, 8 | 16, 1])
