@@ -31,7 +31,7 @@ struct SmallArgs {
     double* lane_aff;  // [NC] in-wave prefix affine maps
     double* wave_x;    // [NG] state at wavefront-unit starts
     double* mid_el;    // [NG] in-block suffixes of the unit totals (NG > kSmallTopBlock)
-    double* blk_val;   // [NB + 1] value function at block starts (NG > kSmallTopBlock)
+    double* blk_val;   // [NB + 1] value function at block starts (NG > kSmallTopBlock, many blocks)
     int64_t NC;        // number of chunks
     int32_t B;         // steps per chunk
     int32_t NG;        // number of wavefront units (64 chunks each)

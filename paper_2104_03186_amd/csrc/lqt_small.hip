@@ -562,10 +562,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_mid(SmallArgs a) {
 }
 
 // wave_val[g] = mid_el[g] anchored on the value at the start of the next
-// block (blk_val, from k_bwd_top over the block totals); wave_val[NG] = the
-// terminal value.
+// block; wave_val[NG] = the terminal value.  That block value comes from
+// blk_val (k_bwd_top over the block totals), or, when chain is set (few
+// blocks), is formed here by anchoring the totals of the later blocks on the
+// terminal value one after another, which saves the top-level launch.
+constexpr int kDownChain = 8;  // most blocks for the chained form
+
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_bwd_down(SmallArgs a, int64_t ld_cst_st) {
+__global__ __launch_bounds__(kBlock) void k_bwd_down(SmallArgs a, int64_t ld_cst_st, int chain) {
     using S = Sym<N>;
     constexpr int VS = S::size + N;
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -575,10 +579,21 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(SmallArgs a, int64_t ld_cst
         LQT_UNROLL for (int i = 0; i < VS; ++i) o[i] = a.cst[ld_cst_st + i];
         return;
     }
-    const double* bv = a.blk_val + (g / kBlock + 1) * VS;
+    const int64_t b = g / kBlock;
     double Sv[S::size], v[N];
-    LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = bv[i];
-    LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = bv[S::size + i];
+    if (chain) {
+        LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = a.cst[ld_cst_st + i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = a.cst[ld_cst_st + S::size + i];
+        for (int64_t bb = a.NB - 1; bb > b; --bb) {  // uniform over a wavefront
+            Elem<N> tb;
+            load_elem<N>(a.mid_el + bb * kBlock * Elem<N>::size, tb);
+            anchor<N>(tb, Sv, v);
+        }
+    } else {
+        const double* bv = a.blk_val + (b + 1) * VS;
+        LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = bv[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = bv[S::size + i];
+    }
     Elem<N> e;
     load_elem<N>(a.mid_el + g * Elem<N>::size, e);
     anchor<N>(e, Sv, v);
@@ -1079,13 +1094,14 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
             Stage st(h, "bwd_mid", s);
             k_bwd_mid<N><<<(unsigned)a.NB, kBlock, 0, s>>>(a);
         }
-        {
+        const int chain = a.NB <= kDownChain ? 1 : 0;
+        if (!chain) {
             Stage st(h, "bwd_top", s);
             k_bwd_top<N><<<1, kBlock, 0, s>>>(a.mid_el, (int64_t)kBlock * Elem<N>::size, a.NB, a.cst + CL::ST,
                                                a.blk_val);
         }
         Stage st(h, "bwd_down", s);
-        k_bwd_down<N><<<(unsigned)((a.NG + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, CL::ST);
+        k_bwd_down<N><<<(unsigned)((a.NG + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, CL::ST, chain);
     } else {
         Stage st(h, "bwd_top", s);
         k_bwd_top<N><<<1, kBlock, 0, s>>>(a.lane_el, (int64_t)kWave * Elem<N>::size, a.NG, a.cst + CL::ST,
