@@ -768,7 +768,25 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
             load_row<N>(a.r + row * N, buf);
         }
     };
-    if (full_wave) {
+    // whole-chunk row preload: the shapes whose down-sweep keeps the rows
+    // without spilling (n m <= 8, every output written)
+    constexpr bool kPreRows = ALL && MODE == kFast && N * M <= 8;
+    if (kPreRows && full_wave && B == 16) {
+        // Every reference row of the chunk is loaded before the first output
+        // store: one counter tracks loads and stores alike, so a wait for a
+        // row loaded behind earlier stores would also wait for those stores,
+        // every step.  Rows are consumed from rr[0], rr[1], two steps per
+        // iteration, then shifted down.
+        double rr[16][N];
+        LQT_UNROLL for (int i = 0; i < 16; ++i) load_row<N>(a.r + (k0 + 15 - i) * N, rr[i]);
+#pragma unroll 1
+        for (int it = 0; it < 8; ++it) {
+            body(true, 15 - 2 * it, rr[0]);
+            body(true, 14 - 2 * it, rr[1]);
+            LQT_UNROLL for (int i = 0; i < 14; ++i)
+                LQT_UNROLL for (int q = 0; q < N; ++q) rr[i][q] = rr[i + 2][q];
+        }
+    } else if (full_wave) {
         fetch(true, B - 1, rA);
         fetch(true, B - 2, rB);
         for (int j = B - 1; j >= 0; j -= 2) {
@@ -970,6 +988,68 @@ __global__ __launch_bounds__(kBlock) void k_fwd_top(SmallArgs a) {
     }
 }
 
+// Long instances with few blocks of kBlock units: k_fwd_mid composes the
+// unit totals within each block (inclusive prefix, one workgroup per block,
+// stored over the backward pass's mid_el, which is no longer needed);
+// k_fwd_down applies the totals of the earlier blocks to x_0 in turn, then
+// the unit's in-block prefix.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_fwd_mid(SmallArgs a) {
+    static_assert(Aff<N>::size <= Elem<N>::size, "the unit prefixes reuse mid_el");
+    __shared__ double sh[kBlock / kWave][Aff<N>::size];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g = g0 + tid;
+    const int nb = (int)(a.NG - g0 < kBlock ? a.NG - g0 : kBlock);
+    Aff<N> agg, t;
+    if (tid < nb) {
+        const int64_t last = ((g + 1) * kWave < a.NC ? (g + 1) * kWave : a.NC) - 1;
+        load_aff<N>(a.lane_aff + last * Aff<N>::size, agg);
+    } else {
+        aff_identity<N>(agg);
+    }
+    for (int d = 1; d < kWave; d <<= 1) {
+        Aff<N> Q = shfl_up_aff<N>(agg, d);
+        if (lane >= d) aff_after<N>(Q, agg);
+    }
+    if (lane == kWave - 1) store_aff<N>(sh[wv], agg);
+    __syncthreads();
+    if (wv > 0) {
+        Aff<N> R;
+        load_aff<N>(sh[0], R);
+        for (int w = 1; w < wv; ++w) {
+            load_aff<N>(sh[w], t);
+            aff_after<N>(R, t);
+            R = t;
+        }
+        aff_after<N>(R, agg);
+    }
+    if (tid < nb) store_aff<N>(a.mid_el + g * Aff<N>::size, agg);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_fwd_down(SmallArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.NG) return;
+    const int64_t b = g / kBlock;
+    double x[N], nx[N];
+    LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = a.x0[i];
+    Aff<N> t;
+    for (int64_t bb = 0; bb < b; ++bb) {  // earlier blocks are full; uniform over a wavefront
+        load_aff<N>(a.mid_el + ((bb + 1) * kBlock - 1) * Aff<N>::size, t);
+        mv<N, N>(t.F, x, nx);
+        LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + t.c[i];
+    }
+    if (g > b * kBlock) {
+        load_aff<N>(a.mid_el + (g - 1) * Aff<N>::size, t);
+        mv<N, N>(t.F, x, nx);
+        LQT_UNROLL for (int i = 0; i < N; ++i) x[i] = nx[i] + t.c[i];
+    }
+    LQT_UNROLL for (int i = 0; i < N; ++i) a.wave_x[g * N + i] = x[i];
+}
+
 template <int N, int M, int MODE, bool ALL, typename OT>
 __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1116,7 +1196,14 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         else k_bwd_final<N, M, MODE, false, OT, false><<<grid, kBlock, 0, s>>>(a);
     }
     if (a.want_fwd) {
-        {
+        if (a.NG > kBlock && a.NB <= kDownChain) {
+            {
+                Stage st(h, "fwd_mid", s);
+                k_fwd_mid<N><<<(unsigned)a.NB, kBlock, 0, s>>>(a);
+            }
+            Stage st(h, "fwd_down", s);
+            k_fwd_down<N><<<(unsigned)((a.NG + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
+        } else {
             Stage st(h, "fwd_top", s);
             k_fwd_top<N><<<1, kBlock, 0, s>>>(a);
         }
@@ -1124,11 +1211,16 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         const bool regs = MODE != kVar && all && even;
         bool fdone = false;
         if constexpr (N % 2 == 0 && M % 2 == 0) {
+            // gain rows of the whole chunk in registers: up to 128 values
             fdone = true;
             if (regs && a.B == 4) k_fwd_final_regs<N, M, 4, OT><<<grid, kBlock, 0, s>>>(a);
             else if (regs && a.B == 8) k_fwd_final_regs<N, M, 8, OT><<<grid, kBlock, 0, s>>>(a);
-            else if (regs && a.B == 16) k_fwd_final_regs<N, M, 16, OT><<<grid, kBlock, 0, s>>>(a);
-            else fdone = false;
+            else if constexpr (M * N <= 8) {
+                if (regs && a.B == 16) k_fwd_final_regs<N, M, 16, OT><<<grid, kBlock, 0, s>>>(a);
+                else fdone = false;
+            } else {
+                fdone = false;
+            }
         }
         if (fdone) {
         } else if (all) k_fwd_final<N, M, MODE, true, OT><<<grid, kBlock, 0, s>>>(a);
