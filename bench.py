@@ -97,12 +97,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu):
-    """One instance n=4, m=2, T=args.T.  Returns the result dict."""
+def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajectory="maps"):
+    """One instance n=4, m=2, T=args.T.  Returns the result dict.  trajectory:
+    the forward pass (closed-loop maps, or forward prefixes of the elements)."""
     n, m, T = 4, 2, args.T
     prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
     osz = 8 if prec == "fp64" else 4
-    plan = api.Plan(n, m, prec=prec, device=0, max_steps=T)
+    plan = api.Plan(n, m, prec=prec, device=0, max_steps=T, trajectory=trajectory)
     dp = api.DeviceProblem(prob)
     do = api.DeviceOutputs(n, m, T, dtype=torch.float64 if osz == 8 else torch.float32)
     stream = torch.cuda.current_stream(0)
@@ -386,6 +387,8 @@ def main():
     ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "copy"), default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
+    ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
+                    help="forward pass of a --workload single run: closed-loop maps or forward prefixes")
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
@@ -419,7 +422,8 @@ def main():
         print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed")), flush=True)
         return
     prec = args.prec or "fp64"
-    main_res = run_single(args, api, inputs, torch, prec, args.steps, args.warmup, not args.no_cpu_baseline)
+    main_res = run_single(args, api, inputs, torch, prec, args.steps, args.warmup, not args.no_cpu_baseline,
+                          trajectory=args.trajectory if args.workload == "single" else "maps")
     out = {
         "metric": "LQT time-steps solved/s (single long instance, parallel scan)",
         "value": round(main_res["value"], 1),
@@ -433,8 +437,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f64 arithmetic, f32 results",
         "data": "synthetic (seeded generators: sinusoid-reference tracking; diagonal-cost random-walk batches)",
-        "config": {"workload": f"single LQT instance nx=4 nu=2 T={args.T} {prec}", "nx": 4, "nu": 2, "T": args.T,
-                   "precision": prec},
+        "config": {"workload": f"single LQT instance nx=4 nu=2 T={args.T} {prec}"
+                               + (", trajectory by forward prefixes" if args.trajectory == "prefix" else ""),
+                   "nx": 4, "nu": 2, "T": args.T, "precision": prec},
         "status": main_res["status"],
         "rel_err": main_res["rel_err"],
         "stages_avg_ms": main_res["stages_avg_ms"],
@@ -445,6 +450,9 @@ def main():
     if args.workload == "all":
         mixed = run_single(args, api, inputs, torch, "mixed", args.steps, args.warmup, False)
         out["single_mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "status", "rel_err", "roofline")}
+        m2 = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, trajectory="prefix")
+        out["single_fp64_forward_prefixes"] = {k: m2[k] for k in ("value", "ms_per_step", "status", "rel_err",
+                                                                  "stages_avg_ms")}
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
         out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")

@@ -74,6 +74,22 @@ typedef enum {
  * in the C and b chains of the combination rule (Section IV-A); the float
  * results halve the output traffic, which bounds the small-n pipeline. */
 
+/* How the optimal trajectory (x, u) is recovered after the backward pass
+ * (Section IV-C).  LQT_TRAJ_MAPS (Method 1): parallel scan of the closed-loop
+ * affine maps x_{k+1} = (F_k - L_k K_k) x_k + c~_k.  LQT_TRAJ_PREFIX
+ * (Method 2): a forward scan of the same LQT elements, initialised by the
+ * element (A, b, C, eta, J) = (0, x_0, 0, 0, 0) (the conditional value
+ * function from the given x_0), then x_k = (I + C_{0,k} S_k)^{-1}(b_{0,k} +
+ * C_{0,k} v_k) and u_k = -K_k x_k + d_k.  The element scan does not depend
+ * on the backward pass.  LQT_TRAJ_PREFIX is provided on the lane pipeline
+ * (nx <= 4, nu <= nx, T >= 8192); other instances that ask for x or u then
+ * fail with LQT_ENOTSUP.  It reads S and v, held in library workspace when
+ * the caller does not take them. */
+typedef enum {
+    LQT_TRAJ_MAPS = 0,
+    LQT_TRAJ_PREFIX = 1
+} lqt_trajectory;
+
 /* Bits of lqt_problem.per_step: a set bit means the matrix has a leading time
  * axis of length T (one matrix per step k = 0..T-1); a clear bit means one
  * matrix serves every step. */
@@ -121,6 +137,7 @@ typedef struct {
     size_t hbm_budget_bytes;  /* cap on library-owned device memory (0: no cap)     */
     int64_t max_steps;        /* workspace is pre-sized for this many total steps   */
     int32_t max_inflight;     /* lqt_submit queue depth (0: default)                */
+    lqt_trajectory trajectory; /* forward pass (0: LQT_TRAJ_MAPS)                   */
 } lqt_plan_desc;
 
 typedef struct lqt_plan_s *lqt_plan_t;

@@ -17,6 +17,7 @@ STATUS_NAMES = {OK: "LQT_OK", EINVAL: "LQT_EINVAL", ENOMEM: "LQT_ENOMEM", ENOTPD
                 ENONFINITE: "LQT_ENONFINITE", EAGAIN: "LQT_EAGAIN", EBUSY: "LQT_EBUSY", EHIP: "LQT_EHIP",
                 ENOTSUP: "LQT_ENOTSUP"}
 PREC_FP64, PREC_MIXED = 0, 1
+TRAJ_MAPS, TRAJ_PREFIX = 0, 1
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
@@ -43,7 +44,7 @@ class StageTime(ctypes.Structure):
 class PlanDesc(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_nx", ctypes.c_int32), ("max_nu", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t), ("max_steps", ctypes.c_int64),
-                ("max_inflight", ctypes.c_int32)]
+                ("max_inflight", ctypes.c_int32), ("trajectory", ctypes.c_int32)]
 
 
 class ServeStats(ctypes.Structure):

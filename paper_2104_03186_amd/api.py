@@ -15,6 +15,7 @@ from . import _lib
 
 FAMILIES = ("S", "v", "K", "d", "x", "u")
 _PREC = {"fp64": _lib.PREC_FP64, "mixed": _lib.PREC_MIXED}
+_TRAJ = {"maps": _lib.TRAJ_MAPS, "prefix": _lib.TRAJ_PREFIX}
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -69,10 +70,15 @@ class Plan:
     """Owns an lqt_plan_t (workspace on one device)."""
 
     def __init__(self, max_nx: int, max_nu: int, prec: str = "fp64", device: int = 0, max_steps: int = 0,
-                 hbm_budget_bytes: int = 0, max_inflight: int = 0):
+                 hbm_budget_bytes: int = 0, max_inflight: int = 0, trajectory: str = "maps"):
+        """trajectory: "maps" (Method 1, scan of the closed-loop affine maps) or
+        "prefix" (Method 2, forward scan of the LQT elements from x_0)."""
         lib = _lib.load()
+        if trajectory not in _TRAJ:
+            raise ValueError(f"trajectory must be one of {sorted(_TRAJ)}")
         d = _lib.PlanDesc(device=device, max_nx=max_nx, max_nu=max_nu, prec=_PREC[prec],
-                          hbm_budget_bytes=hbm_budget_bytes, max_steps=max_steps, max_inflight=max_inflight)
+                          hbm_budget_bytes=hbm_budget_bytes, max_steps=max_steps, max_inflight=max_inflight,
+                          trajectory=_TRAJ[trajectory])
         h = ctypes.c_void_p()
         _lib.check(lib.lqt_plan(ctypes.byref(d), ctypes.byref(h)), None)
         self._h = h

@@ -37,6 +37,9 @@ struct SmallArgs {
     int32_t NG;        // number of wavefront units (64 chunks each)
     int32_t NB;        // blocks of kSmallTopBlock units
     int32_t want_fwd;  // run the forward pass
+    int32_t traj;      // forward pass: 0 = scan of the closed-loop maps, 1 = forward prefixes
+    double* m2_el;     // [NC] in-wave prefixes of the chunk elements (traj 1)
+    double* m2_val;    // [NG] (C, b) of the forward prefix at wavefront-unit starts (traj 1)
 };
 
 // Optional per-kernel timing hook: begin/end are called on the host around

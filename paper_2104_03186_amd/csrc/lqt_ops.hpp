@@ -55,6 +55,17 @@ LQT_DI void load_elem(const double* p, Elem<N>& x) {
 }
 
 template <int N>
+LQT_DI Elem<N> shfl_up_elem(const Elem<N>& x, int d) {
+    Elem<N> y;
+    LQT_UNROLL for (int i = 0; i < N * N; ++i) y.A[i] = __shfl_up(x.A[i], d, 64);
+    LQT_UNROLL for (int i = 0; i < N; ++i) y.b[i] = __shfl_up(x.b[i], d, 64);
+    LQT_UNROLL for (int i = 0; i < Elem<N>::NS; ++i) y.C[i] = __shfl_up(x.C[i], d, 64);
+    LQT_UNROLL for (int i = 0; i < N; ++i) y.e[i] = __shfl_up(x.e[i], d, 64);
+    LQT_UNROLL for (int i = 0; i < Elem<N>::NS; ++i) y.J[i] = __shfl_up(x.J[i], d, 64);
+    return y;
+}
+
+template <int N>
 LQT_DI Elem<N> shfl_down_elem(const Elem<N>& x, int d) {
     Elem<N> y;
     LQT_UNROLL for (int i = 0; i < N * N; ++i) y.A[i] = __shfl_down(x.A[i], d, 64);
@@ -305,6 +316,65 @@ LQT_DI void anchor(const Elem<N>& x, double* Sv, double* v) {
     }
     LQT_UNROLL for (int i = 0; i < N; ++i) v[i] = nv[i] + x.e[i];
     LQT_UNROLL for (int i = 0; i < S::size; ++i) Sv[i] = nS[i];
+}
+
+// Forward prefix from a fixed initial state (Method 2 of Section IV-C): the
+// conditional value function V_{0->k} initialised with the element
+// (0, x_0, 0, 0, 0) keeps A = eta = J = 0 under every later combination, so
+// it is carried as (b, C).  (b, C) <- (0, b, C, 0, 0) (x) e is the
+// combination rule with that left operand:
+//   M = I + C J_e,  b' = A_e M^{-1}(b + C eta_e) + b_e,
+//   C' = A_e M^{-1} C A_e^T + C_e.
+template <int N>
+LQT_DI void fanchor(const Elem<N>& e, double* b, double* Cs) {
+    using S = Sym<N>;
+    double Mm[N * N], Mi[N * N];
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int j = 0; j < N; ++j) {
+        double s = (i == j) ? 1.0 : 0.0;
+        LQT_UNROLL for (int k = 0; k < N; ++k) s = fma(Cs[S::at(i, k)], e.J[S::at(k, j)], s);
+        Mm[i * N + j] = s;
+    }
+    inv_pivot<N>(Mm, Mi);
+    double t[N], t2[N], nb[N];
+    smv<N>(Cs, e.e, t);
+    LQT_UNROLL for (int i = 0; i < N; ++i) t[i] += b[i];
+    mv<N, N>(Mi, t, t2);
+    mv<N, N>(e.A, t2, nb);
+    double Q[N * N], R[N * N];
+    LQT_UNROLL for (int i = 0; i < N; ++i)  // Q = M^{-1} C
+    LQT_UNROLL for (int j = 0; j < N; ++j) {
+        double s = Mi[i * N] * Cs[S::at(0, j)];
+        LQT_UNROLL for (int k = 1; k < N; ++k) s = fma(Mi[i * N + k], Cs[S::at(k, j)], s);
+        Q[i * N + j] = s;
+    }
+    mm<N, N, N>(e.A, Q, R);
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int j = i; j < N; ++j) {
+        double s = e.C[S::at(i, j)];
+        LQT_UNROLL for (int k = 0; k < N; ++k) s = fma(R[i * N + k], e.A[j * N + k], s);
+        Cs[S::at(i, j)] = s;
+    }
+    LQT_UNROLL for (int i = 0; i < N; ++i) b[i] = nb[i] + e.b[i];
+}
+
+// Optimal state from the forward prefix (b, C) and the value function
+// (S_k full, v_k) at the same step (lemma on Method 2 of Section IV-C):
+// x_k = (I + C S_k)^{-1}(b + C v_k).
+template <int N>
+LQT_DI void prefix_state(const double* b, const double* Cs, const double* Sk, const double* vk, double* x) {
+    using S = Sym<N>;
+    double Mm[N * N], Mi[N * N], t[N];
+    LQT_UNROLL for (int i = 0; i < N; ++i)
+    LQT_UNROLL for (int j = 0; j < N; ++j) {
+        double s = (i == j) ? 1.0 : 0.0;
+        LQT_UNROLL for (int k = 0; k < N; ++k) s = fma(Cs[S::at(i, k)], Sk[k * N + j], s);
+        Mm[i * N + j] = s;
+    }
+    inv_pivot<N>(Mm, Mi);
+    smv<N>(Cs, vk, t);
+    LQT_UNROLL for (int i = 0; i < N; ++i) t[i] += b[i];
+    mv<N, N>(Mi, t, x);
 }
 
 // One down-sweep application a_k (x) (0, 0, 0, v_{k+1}, S_{k+1}) written in

@@ -218,12 +218,15 @@ int chunk_length(int64_t T) {
 }
 
 struct Layout {
-    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, total;
+    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, m2_el, m2_val, S, v, total;
     int64_t NC;
     int B, NG, NB;
 };
 
-Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
+// m2: forward pass by prefixes (Method 2), which reads S and v (scratch when
+// the caller does not take them).
+Layout layout_for(const lqt_problem& p, bool need_K, bool need_d, bool m2 = false, bool need_S = false,
+                  bool need_v = false) {
     using namespace lqt;
     Layout L{};
     const int n = p.nx, m = p.nu;
@@ -249,6 +252,10 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d) {
     L.blk_val = take(blocks ? (size_t)(L.NB + 1) * small_val_doubles(n) : 0);
     L.K = take(need_K ? (size_t)p.T * m * n : 0);
     L.d = take(need_d ? (size_t)p.T * m : 0);
+    L.m2_el = take(m2 ? (size_t)L.NC * small_elem_doubles(n) : 0);
+    L.m2_val = take(m2 ? (size_t)L.NG * small_val_doubles(n) : 0);
+    L.S = take(m2 && need_S ? (size_t)(p.T + 1) * n * n : 0);
+    L.v = take(m2 && need_v ? (size_t)(p.T + 1) * n : 0);
     L.total = off;
     return L;
 }
@@ -278,7 +285,8 @@ struct BatchSize {
     explicit BatchSize(lqt_plan_t pl) : plan(pl) {}
     void add(const lqt_problem& p, const lqt_outputs& o) {
         if (path_of(p) == Path::Small) {
-            small = std::max(small, align_up(layout_for(p, !o.K, !o.d).total));
+            const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && (o.x || o.u);
+            small = std::max(small, align_up(layout_for(p, !o.K, !o.d, m2, !o.S, !o.v).total));
         } else {
             wave += wave_bytes(plan, p) + wave_kd_bytes(p, o);
             ++nwave;
@@ -295,6 +303,10 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
+    if (plan->desc.trajectory == LQT_TRAJ_PREFIX && path_of(p) != Path::Small && (o.x || o.u))
+        return fail(plan, LQT_ENOTSUP,
+                    "instance %d: the forward-prefix trajectory is provided on the n <= 4 lane pipeline only "
+                    "(nx=%d nu=%d T=%lld)", idx, p.nx, p.nu, (long long)p.T);
     if (path_of(p) == Path::Wave) {
         if (std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
             return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
@@ -351,13 +363,15 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
                       int32_t* status_override) {
     const bool fwd = o.x || o.u;
     const bool need_K = !o.K, need_d = !o.d;
-    Layout L = layout_for(p, need_K, need_d);
+    const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && fwd;
+    Layout L = layout_for(p, need_K, need_d, m2, !o.S, !o.v);
     lqt::SmallArgs a{};
     a.F = p.F; a.c = p.c; a.L = p.L; a.U = p.U; a.H = p.H; a.X = p.X; a.r = p.r;
     a.HT = p.HT; a.XT = p.XT; a.rT = p.rT; a.x0 = p.x0;
     a.T = p.T; a.n = p.nx; a.m = p.nu; a.p = p.ny; a.pT = p.nyT;
     a.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-    a.S = o.S; a.v = o.v;
+    a.S = o.S ? o.S : (m2 ? (void*)(base + L.S) : nullptr);
+    a.v = o.v ? o.v : (m2 ? (void*)(base + L.v) : nullptr);
     a.K = o.K ? o.K : (void*)(base + L.K);
     a.d = o.d ? o.d : (void*)(base + L.d);
     a.x = o.x; a.u = o.u;
@@ -373,6 +387,9 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.blk_val = (double*)(base + L.blk_val);
     a.NC = L.NC; a.B = L.B; a.NG = L.NG; a.NB = L.NB;
     a.want_fwd = fwd ? 1 : 0;
+    a.traj = m2 ? 1 : 0;
+    a.m2_el = (double*)(base + L.m2_el);
+    a.m2_val = (double*)(base + L.m2_val);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr);
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -649,6 +666,8 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
         return fail(nullptr, LQT_ENOTSUP, "lqt_plan: max_nx=%d exceeds the library's limit %d", desc->max_nx, kMaxNx);
     if (desc->prec != LQT_PREC_FP64 && desc->prec != LQT_PREC_MIXED)
         return fail(nullptr, LQT_EINVAL, "lqt_plan: unknown precision %d", (int)desc->prec);
+    if (desc->trajectory != LQT_TRAJ_MAPS && desc->trajectory != LQT_TRAJ_PREFIX)
+        return fail(nullptr, LQT_EINVAL, "lqt_plan: unknown trajectory method %d", (int)desc->trajectory);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -671,7 +690,8 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
             for (int m = 1; m <= desc->max_nu; ++m)
                 if (lqt::small_supported(n, m)) {
                     probe.nx = n; probe.nu = m; probe.ny = n;
-                    need = std::max(need, layout_for(probe, true, true).total);
+                    need = std::max(need, layout_for(probe, true, true, desc->trajectory == LQT_TRAJ_PREFIX,
+                                                     true, true).total);
                 }
         // and for one wavefront-path instance of the largest dimensions
         {

@@ -1147,6 +1147,159 @@ struct Stage {
     }
 };
 
+// ---- trajectory by forward prefixes (Method 2 of Section IV-C) --------------
+//
+// The forward pass reuses the scan elements: V_{0->k} = i (x) a_0 (x) ... (x)
+// a_{k-1} with the initial-state element i = (0, x_0, 0, 0, 0), carried as
+// (b, C) (fanchor), and x_k = (I + C S_k)^{-1}(b + C v_k) with the value
+// function of the backward pass.  Structure as in the backward pass, in the
+// other direction: k_m2_reduce folds each chunk left to right and scans the
+// wavefront (inclusive prefixes), k_m2_top forms (b, C) at every wavefront
+// unit's first step, k_m2_final walks each chunk forward.  The element scan
+// does not depend on the backward pass.
+
+template <int N, int M, int MODE>
+__global__ __launch_bounds__(kBlock) void k_m2_reduce(SmallArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool active = c < a.NC;
+    Elem<N> P;
+    if (active) {
+        Step<N, M> st;
+        if constexpr (MODE != kVar) load_invariant<N, M>(a, st);
+        const int64_t k0 = c * a.B;
+        const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
+        load_step<N, M, MODE>(a, k0, st);
+        step_elem<N, M>(st, P);
+        for (int64_t k = k0 + 1; k < k1; ++k) {
+            load_step<N, M, MODE>(a, k, st);
+            Elem<N> E;
+            step_elem<N, M>(st, E);
+            combine<N>(P, E);  // E <- P (x) E
+            P = E;
+        }
+    } else {
+        set_identity<N>(P);
+    }
+    // prefix across the wavefront: lane l ends with E_0 (x) ... (x) E_l
+    for (int d = 1; d < kWave; d <<= 1) {
+        Elem<N> Q = shfl_up_elem<N>(P, d);
+        if (lane >= d) combine<N>(Q, P);  // P <- Q (x) P
+    }
+    if (active) store_elem<N>(a.m2_el + c * Elem<N>::size, P);
+}
+
+// One workgroup: (C, b) of V_{0->k} at the first step of every wavefront unit
+// g (m2_val[g]), from the unit totals (the in-wave prefix of each unit's last
+// lane) and x_0.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_m2_top(SmallArgs a) {
+    using S = Sym<N>;
+    constexpr int VS = S::size + N;
+    __shared__ double sh[kBlock / kWave][Elem<N>::size];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int NG = a.NG;
+    const int q = (NG + kBlock - 1) / kBlock;
+    const int lo = tid * q < NG ? tid * q : NG;
+    const int hi = lo + q < NG ? lo + q : NG;
+    auto unit_total = [&](int g, Elem<N>& t) {
+        const int64_t last = ((int64_t)(g + 1) * kWave < a.NC ? (int64_t)(g + 1) * kWave : a.NC) - 1;
+        load_elem<N>(a.m2_el + last * Elem<N>::size, t);
+    };
+    Elem<N> agg, t;
+    set_identity<N>(agg);
+    for (int g = lo; g < hi; ++g) {
+        unit_total(g, t);
+        combine<N>(agg, t);  // t <- agg (x) t
+        agg = t;
+    }
+    for (int d = 1; d < kWave; d <<= 1) {
+        Elem<N> Q = shfl_up_elem<N>(agg, d);
+        if (lane >= d) combine<N>(Q, agg);
+    }
+    if (lane == kWave - 1) store_elem<N>(sh[wv], agg);
+    __syncthreads();
+    // prefix of everything before this thread's range, anchored on x_0
+    Elem<N> R;
+    set_identity<N>(R);
+    for (int w = 0; w < wv; ++w) {
+        load_elem<N>(sh[w], t);
+        combine<N>(R, t);
+        R = t;
+    }
+    Elem<N> prev = shfl_up_elem<N>(agg, 1);
+    if (lane == 0) set_identity<N>(prev);
+    combine<N>(R, prev);  // prev <- R (x) prev
+    double b[N], Cs[S::size];
+    LQT_UNROLL for (int i = 0; i < N; ++i) b[i] = a.x0[i];
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) Cs[i] = 0.0;
+    fanchor<N>(prev, b, Cs);
+    for (int g = lo; g < hi; ++g) {
+        double* o = a.m2_val + (int64_t)g * VS;
+        LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = Cs[i];
+        LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = b[i];
+        unit_total(g, t);
+        fanchor<N>(t, b, Cs);
+    }
+}
+
+// Lane c: (b, C) at its chunk's first step (its unit's value advanced by the
+// in-wave prefix of the lanes before it), then per step x_k from S_k, v_k,
+// u_k = -K_k x_k + d_k, and (b, C) advanced by the step's element.
+template <int N, int M, int MODE, typename OT>
+__global__ __launch_bounds__(kBlock) void k_m2_final(SmallArgs a) {
+    using S = Sym<N>;
+    constexpr int VS = S::size + N;
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.NC) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const OT* const iS = (const OT*)a.S;
+    const OT* const iV = (const OT*)a.v;
+    const OT* const iK = (const OT*)a.K;
+    const OT* const iD = (const OT*)a.d;
+    OT* const oX = (OT*)a.x;
+    OT* const oU = (OT*)a.u;
+    double b[N], Cs[S::size];
+    const double* gv = a.m2_val + (c / kWave) * VS;
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) Cs[i] = gv[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) b[i] = gv[S::size + i];
+    if (lane > 0) {
+        Elem<N> e;
+        load_elem<N>(a.m2_el + (c - 1) * Elem<N>::size, e);
+        fanchor<N>(e, b, Cs);
+    }
+    Step<N, M> st;
+    if constexpr (MODE != kVar) load_invariant<N, M>(a, st);
+    const int64_t k0 = c * a.B;
+    const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
+    const int64_t kend = (k1 == a.T) ? k1 : k1 - 1;  // the last chunk also gives x_T
+    for (int64_t k = k0; k <= kend; ++k) {
+        double Sk[N * N], vk[N], x[N];
+        load_row<N * N>(iS + k * N * N, Sk);
+        load_row<N>(iV + k * N, vk);
+        prefix_state<N>(b, Cs, Sk, vk, x);
+        if (oX) store_row<N>(oX + k * N, x);
+        if (k == a.T) break;
+        if (oU) {
+            double K[M * N], d[M], u[M];
+            load_row<M * N>(iK + k * M * N, K);
+            load_row<M>(iD + k * M, d);
+            LQT_UNROLL for (int i = 0; i < M; ++i) {
+                double sacc = d[i];
+                LQT_UNROLL for (int j = 0; j < N; ++j) sacc = fma(-K[i * N + j], x[j], sacc);
+                u[i] = sacc;
+            }
+            store_row<M>(oU + k * M, u);
+        }
+        load_step<N, M, MODE>(a, k, st);
+        Elem<N> E;
+        step_elem<N, M>(st, E);
+        fanchor<N>(E, b, Cs);
+    }
+}
+
 template <int N, int M, int MODE, typename OT>
 static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     using CL = CstLayout<N, M>;
@@ -1195,7 +1348,18 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         else if (hasc) k_bwd_final<N, M, MODE, false, OT, true><<<grid, kBlock, 0, s>>>(a);
         else k_bwd_final<N, M, MODE, false, OT, false><<<grid, kBlock, 0, s>>>(a);
     }
-    if (a.want_fwd) {
+    if (a.want_fwd && a.traj == 1) {
+        {
+            Stage st(h, "m2_reduce", s);
+            k_m2_reduce<N, M, MODE><<<grid, kBlock, 0, s>>>(a);
+        }
+        {
+            Stage st(h, "m2_top", s);
+            k_m2_top<N><<<1, kBlock, 0, s>>>(a);
+        }
+        Stage st(h, "m2_final", s);
+        k_m2_final<N, M, MODE, OT><<<grid, kBlock, 0, s>>>(a);
+    } else if (a.want_fwd) {
         if (a.NG > kBlock && a.NB <= kDownChain) {
             {
                 Stage st(h, "fwd_mid", s);
