@@ -77,8 +77,10 @@ def stage_bytes_per_step(stage, n, m, p, osz=8):
         return 8 * p + osz * (n * n + n + m * n + m)
     if stage == "fwd_final":   # reads K_k, d_k, writes x_k, u_k
         return osz * (m * n + m + n + m)
-    if stage in ("bwd_reduce", "prep_varying"):   # reads r_k
+    if stage in ("bwd_reduce", "prep_varying", "m2_reduce"):   # reads r_k
         return 8 * p
+    if stage == "m2_final":    # reads r_k, S_k, v_k, K_k, d_k, writes x_k, u_k
+        return 8 * p + osz * (n * n + n + m * n + m + n + m)
     return 0
 
 

@@ -43,6 +43,10 @@ LQT_DI void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Wait until every outstanding vector-memory request of the wavefront has
+// completed (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).
+LQT_DI void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 LQT_DI void raise_status(int32_t* st, int32_t code) {
     if (st) atomicCAS(st, 0, code);  // first failure wins
 }
@@ -1275,29 +1279,75 @@ __global__ __launch_bounds__(kBlock) void k_m2_final(SmallArgs a) {
     const int64_t k0 = c * a.B;
     const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
     const int64_t kend = (k1 == a.T) ? k1 : k1 - 1;  // the last chunk also gives x_T
-    for (int64_t k = k0; k <= kend; ++k) {
-        double Sk[N * N], vk[N], x[N];
-        load_row<N * N>(iS + k * N * N, Sk);
-        load_row<N>(iV + k * N, vk);
-        prefix_state<N>(b, Cs, Sk, vk, x);
-        if (oX) store_row<N>(oX + k * N, x);
-        if (k == a.T) break;
-        if (oU) {
-            double K[M * N], d[M], u[M];
-            load_row<M * N>(iK + k * M * N, K);
-            load_row<M>(iD + k * M, d);
-            LQT_UNROLL for (int i = 0; i < M; ++i) {
-                double sacc = d[i];
-                LQT_UNROLL for (int j = 0; j < N; ++j) sacc = fma(-K[i * N + j], x[j], sacc);
-                u[i] = sacc;
-            }
-            store_row<M>(oU + k * M, u);
+    // Software pipeline: at the top of step k one explicit wait covers the
+    // rows of step k (and every earlier request); then step k-1's x, u are
+    // stored and step k+1's rows requested, and step k's arithmetic runs with
+    // no further wait.  A wait thus never drains a request younger than one
+    // step (one counter tracks loads and stores alike, so the wait the
+    // compiler would place before the first use of a row would also drain
+    // the stores and loads issued just before it).
+    struct Rows {
+        double S[N * N], v[N], K[M * N], d[M], r[N];
+    };
+    auto fetch = [&](int64_t k, Rows& R) {
+        load_row<N * N>(iS + k * N * N, R.S);
+        load_row<N>(iV + k * N, R.v);
+        if (k < a.T) {
+            load_row<M * N>(iK + k * M * N, R.K);
+            load_row<M>(iD + k * M, R.d);
+            if constexpr (MODE == kFast) load_row<N>(a.r + k * N, R.r);
         }
-        load_step<N, M, MODE>(a, k, st);
+    };
+    double px[N], pu[M];
+    bool pend_x = false, pend_u = false;
+    int64_t pk = 0;
+    auto flush = [&]() {
+        if (pend_x) store_row<N>(oX + pk * N, px);
+        if (pend_u) store_row<M>(oU + pk * M, pu);
+        pend_x = pend_u = false;
+    };
+    double Wl[N * N];  // W = H^T X (square H, X)
+    if constexpr (MODE == kFast) {
+        LQT_UNROLL for (int i = 0; i < N * N; ++i) Wl[i] = a.cst[CstLayout<N, M>::W + i];
+    }
+    auto step = [&](int64_t k, const Rows& R) {
+        double x[N];
+        prefix_state<N>(b, Cs, R.S, R.v, x);
+        LQT_UNROLL for (int i = 0; i < N; ++i) px[i] = x[i];
+        pk = k;
+        pend_x = oX != nullptr;
+        if (k == a.T) return;
+        LQT_UNROLL for (int i = 0; i < M; ++i) {
+            double sacc = R.d[i];
+            LQT_UNROLL for (int j = 0; j < N; ++j) sacc = fma(-R.K[i * N + j], x[j], sacc);
+            pu[i] = sacc;
+        }
+        pend_u = oU != nullptr;
+        if constexpr (MODE == kFast) {
+            eta_sq<N>(Wl, R.r, st.e);
+        } else {
+            load_step<N, M, MODE>(a, k, st);
+        }
         Elem<N> E;
         step_elem<N, M>(st, E);
         fanchor<N>(E, b, Cs);
+    };
+    Rows RA, RB;
+    fetch(k0, RA);
+    for (int64_t k = k0; k <= kend; k += 2) {
+        vm_wait_all();
+        flush();
+        if (k + 1 <= kend) fetch(k + 1, RB);
+        step(k, RA);
+        if (k + 1 > kend) break;
+        vm_wait_all();
+        flush();
+        if (k + 2 <= kend) fetch(k + 2, RA);
+        step(k + 1, RB);
     }
+    vm_wait_all();
+    flush();
+
 }
 
 template <int N, int M, int MODE, typename OT>
