@@ -81,7 +81,9 @@ typedef enum {
  * element (A, b, C, eta, J) = (0, x_0, 0, 0, 0) (the conditional value
  * function from the given x_0), then x_k = (I + C_{0,k} S_k)^{-1}(b_{0,k} +
  * C_{0,k} v_k) and u_k = -K_k x_k + d_k.  The element scan does not depend
- * on the backward pass.  LQT_TRAJ_PREFIX is provided on the lane pipeline
+ * on the backward pass and runs on a second stream owned by the plan,
+ * concurrently with it (joined before the forward walk, so the solve stays
+ * ordered on the caller's stream).  LQT_TRAJ_PREFIX is provided on the lane pipeline
  * (nx <= 4, nu <= nx, T >= 8192); other instances that ask for x or u then
  * fail with LQT_ENOTSUP.  It reads S and v, held in library workspace when
  * the caller does not take them. */

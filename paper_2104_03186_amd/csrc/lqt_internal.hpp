@@ -84,6 +84,14 @@ size_t small_der_doubles(int n, int m);
 size_t small_elem_doubles(int n);
 size_t small_aff_doubles(int n);
 size_t small_val_doubles(int n);
-hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook);
+// A second stream and two events owned by the plan: the forward element scan
+// of the prefix trajectory runs on `side`, concurrently with the backward
+// pass on the solve's stream (fork after the constants, join before the
+// forward walk).
+struct SideStream {
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook, const SideStream* side = nullptr);
 
 }  // namespace lqt

@@ -187,6 +187,8 @@ struct lqt_plan_s {
     uint64_t next_ticket = 1;
     lqt_serve_stats stats{};
     int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
+    lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
+    bool has_side = false;
 };
 
 namespace {
@@ -391,7 +393,7 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.m2_el = (double*)(base + L.m2_el);
     a.m2_val = (double*)(base + L.m2_val);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
-    hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr);
+    hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr, plan->has_side ? &plan->side : nullptr);
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return LQT_OK;
 }
@@ -680,6 +682,23 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     if (!p) return fail(nullptr, LQT_ENOMEM, "lqt_plan: out of host memory");
     p->desc = *desc;
     if (p->desc.max_inflight <= 0) p->desc.max_inflight = kDefaultQueue;
+    if (desc->trajectory == LQT_TRAJ_PREFIX) {
+        // a failure leaves the element scan on the solve's own stream
+        lqt::SideStream& sd = p->side;
+        if (hipStreamCreateWithFlags(&sd.side, hipStreamNonBlocking) == hipSuccess) {
+            if (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) == hipSuccess) {
+                if (hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) == hipSuccess) {
+                    p->has_side = true;
+                } else {
+                    (void)hipEventDestroy(sd.fork);
+                    (void)hipStreamDestroy(sd.side);
+                }
+            } else {
+                (void)hipStreamDestroy(sd.side);
+            }
+        }
+        (void)hipGetLastError();
+    }
     if (desc->max_steps > 0) {
         lqt_problem probe{};
         probe.nx = desc->max_nx; probe.nu = desc->max_nu; probe.ny = desc->max_nx; probe.nyT = desc->max_nx;
@@ -707,6 +726,11 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
         lqt_status st = ensure_ws(p, p->main, need);
         if (st != LQT_OK) {
             g_create_error = p->err;
+            if (p->has_side) {
+                (void)hipStreamDestroy(p->side.side);
+                (void)hipEventDestroy(p->side.fork);
+                (void)hipEventDestroy(p->side.join);
+            }
             delete p;
             return st;
         }
@@ -849,6 +873,11 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
         arena_release(s.arena);
     }
     if (plan->pool) (void)hipFree(plan->pool);
+    if (plan->has_side) {
+        (void)hipStreamDestroy(plan->side.side);
+        (void)hipEventDestroy(plan->side.fork);
+        (void)hipEventDestroy(plan->side.join);
+    }
     for (auto& r : plan->prof.pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);

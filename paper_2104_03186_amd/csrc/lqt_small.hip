@@ -1351,7 +1351,7 @@ __global__ __launch_bounds__(kBlock) void k_m2_final(SmallArgs a) {
 }
 
 template <int N, int M, int MODE, typename OT>
-static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
+static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h, const SideStream* side) {
     using CL = CstLayout<N, M>;
     const unsigned grid = (unsigned)((a.NC + kBlock - 1) / kBlock);
     const bool all = a.S && a.v && a.x && a.u;
@@ -1367,6 +1367,21 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
     } else {
         Stage st(h, "prep_invariant", s);
         k_prep_invariant<N, M><<<1, 64, 0, s>>>(a);
+    }
+    // forward element scan of the prefix trajectory: independent of the
+    // backward pass, on the side stream when the plan provides one
+    const bool m2 = a.want_fwd && a.traj == 1;
+    hipStream_t s2 = s;
+    if (m2 && side && hipEventRecord(side->fork, s) == hipSuccess &&
+        hipStreamWaitEvent(side->side, side->fork, 0) == hipSuccess)
+        s2 = side->side;
+    if (m2) {
+        {
+            Stage st(h, "m2_reduce", s2);
+            k_m2_reduce<N, M, MODE><<<grid, kBlock, 0, s2>>>(a);
+        }
+        Stage st(h, "m2_top", s2);
+        k_m2_top<N><<<1, kBlock, 0, s2>>>(a);
     }
     {
         Stage st(h, "bwd_reduce", s);
@@ -1398,14 +1413,10 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
         else if (hasc) k_bwd_final<N, M, MODE, false, OT, true><<<grid, kBlock, 0, s>>>(a);
         else k_bwd_final<N, M, MODE, false, OT, false><<<grid, kBlock, 0, s>>>(a);
     }
-    if (a.want_fwd && a.traj == 1) {
-        {
-            Stage st(h, "m2_reduce", s);
-            k_m2_reduce<N, M, MODE><<<grid, kBlock, 0, s>>>(a);
-        }
-        {
-            Stage st(h, "m2_top", s);
-            k_m2_top<N><<<1, kBlock, 0, s>>>(a);
+    if (m2) {
+        if (s2 != s) {  // join: the walk needs the element scan
+            (void)hipEventRecord(side->join, s2);
+            (void)hipStreamWaitEvent(s, side->join, 0);
         }
         Stage st(h, "m2_final", s);
         k_m2_final<N, M, MODE, OT><<<grid, kBlock, 0, s>>>(a);
@@ -1443,17 +1454,17 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h) {
 }
 
 template <int N, int M, typename OT>
-static void run_typed(const SmallArgs& a, hipStream_t s, const StageHook* h) {
+static void run_typed(const SmallArgs& a, hipStream_t s, const StageHook* h, const SideStream* side) {
     const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
-    if (var) run_mode<N, M, kVar, OT>(a, s, h);
-    else if (a.p == N) run_mode<N, M, kFast, OT>(a, s, h);
-    else run_mode<N, M, kInv, OT>(a, s, h);
+    if (var) run_mode<N, M, kVar, OT>(a, s, h, side);
+    else if (a.p == N) run_mode<N, M, kFast, OT>(a, s, h, side);
+    else run_mode<N, M, kInv, OT>(a, s, h, side);
 }
 
 template <int N, int M>
-static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* h) {
-    if (a.f32) run_typed<N, M, float>(a, s, h);
-    else run_typed<N, M, double>(a, s, h);
+static hipError_t run_small(const SmallArgs& a, hipStream_t s, const StageHook* h, const SideStream* side) {
+    if (a.f32) run_typed<N, M, float>(a, s, h, side);
+    else run_typed<N, M, double>(a, s, h, side);
     return hipGetLastError();
 }
 
@@ -1484,8 +1495,8 @@ size_t small_elem_doubles(int n) { return (size_t)n * n + 2 * n + (size_t)n * (n
 size_t small_aff_doubles(int n) { return (size_t)n * n + n; }
 size_t small_val_doubles(int n) { return (size_t)n * (n + 1) / 2 + n; }
 
-hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook) {
-#define X(N, M) if (a.n == N && a.m == M) return run_small<N, M>(a, s, hook);
+hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook, const SideStream* side) {
+#define X(N, M) if (a.n == N && a.m == M) return run_small<N, M>(a, s, hook, side);
     LQT_SMALL_CASES(X)
 #undef X
     return hipErrorInvalidValue;
