@@ -65,6 +65,8 @@ def _load():
     i32, i64, u32 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
     lib.oracle_solve.argtypes = [i32, i32, i32, i32, i64, u32] + [dp] * 17
     lib.oracle_solve.restype = i32
+    lib.oracle_solve_gen.argtypes = [i32, i32, i32, i32, i64, u32] + [dp] * 19
+    lib.oracle_solve_gen.restype = i32
     lib.oracle_element.argtypes = [i32, i32, i32, i32, i64, u32, i64] + [dp] * 11
     lib.oracle_element.restype = i32
     lib.oracle_combine.argtypes = [i32, dp, dp, dp]
@@ -97,7 +99,9 @@ def _inputs(prob):
 
 
 def solve(prob) -> dict:
-    """Sequential FP64 solution (Section II-B).  Returns S, v, K, d, x, u."""
+    """Sequential FP64 solution (Section II-B; with a cross term M or control
+    reference s, the generalised stage cost of Section IV-D).  Returns S, v,
+    K, d, x, u."""
     lib = _load()
     n, m, T = int(prob.n), int(prob.m), int(prob.T)
     out = {
@@ -107,9 +111,17 @@ def solve(prob) -> dict:
     }
     ins = _inputs(prob)
     x0 = _arr(prob.x0)
-    rc = lib.oracle_solve(n, m, int(prob.p), int(prob.pT), T, int(prob.per_step),
-                          *[_p(a) for a in ins], _p(x0),
-                          *[_p(out[k]) for k in ("S", "v", "K", "d", "x", "u")])
+    M = getattr(prob, "M", None)
+    s = getattr(prob, "s", None)
+    if M is None and s is None:
+        rc = lib.oracle_solve(n, m, int(prob.p), int(prob.pT), T, int(prob.per_step),
+                              *[_p(a) for a in ins], _p(x0),
+                              *[_p(out[k]) for k in ("S", "v", "K", "d", "x", "u")])
+    else:  # generalised stage cost (Section IV-D)
+        Mz = _arr(M) if M is not None else np.zeros((int(prob.p), m))
+        rc = lib.oracle_solve_gen(n, m, int(prob.p), int(prob.pT), T, int(prob.per_step),
+                                  *[_p(a) for a in ins], _p(x0), _p(Mz), _p(_arr(s)),
+                                  *[_p(out[k]) for k in ("S", "v", "K", "d", "x", "u")])
     if rc != OK:
         raise OracleError(rc)
     return out

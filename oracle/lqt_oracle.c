@@ -21,6 +21,10 @@
  *  - oracle_combine: the LQT associative operator of Section IV-A (lemma on
  *    the LQT combination rule), evaluated literally with two LU solves.
  *  - oracle_cost: the total cost of the problem statement, Section II-B.
+ *  - oracle_solve_gen: the sequential solution for the generalised stage
+ *    cost with a state-control cross term and a control reference (the
+ *    extension to more general cost functions, Section IV-D), by dynamic
+ *    programming written out from that cost.
  *
  * Every routine is a direct transcription of a definition: no blocking, no
  * fusion, no reordering.  All arithmetic is IEEE double precision.
@@ -278,6 +282,137 @@ int oracle_solve(int n, int m, int p, int pT, int64_t T, uint32_t per_step,
 done:
     free(XH); free(Xr); free(SL); free(Mk); free(SF); free(Ft); free(Sc);
     free(w); free(Lw); free(Q); free(hq); free(t1); free(t2);
+    return rc;
+}
+
+/* ---- generalised stage cost, Section IV-D ------------------------------- */
+
+/*
+ * The sequential solution for the stage cost with a state-control cross term
+ * and a control reference (the extension to more general cost functions):
+ *   l_k = 1/2 (H x - r)^T X (H x - r) + (H x - r)^T M (u - s)
+ *         + 1/2 (u - s)^T U (u - s),
+ * M [p][m] (or [T][p][m] with per-step bit 64), s [T][m] (NULL means 0).
+ * Dynamic programming written out from that cost (not through the paper's
+ * transformation to the standard form, which the tests check against it):
+ * with V_{k+1}(x) = 1/2 x^T S x - v^T x, the step cost plus V_{k+1}(F x + c +
+ * L u) is 1/2 x^T Aq x + x^T Bq u + 1/2 u^T W u - a^T x - b^T u + const,
+ *   Aq = H^T X H + F^T S F,   Bq = H^T M + F^T S L,   W = U + L^T S L,
+ *   a = H^T X r + H^T M s + F^T (v - S c),   b = M^T r + U s + L^T (v - S c),
+ * minimised by u = -K x + d, K = W^{-1} Bq^T, d = W^{-1} b, giving
+ *   S_k = Aq - Bq K (made exactly symmetric),  v_k = a - Bq d.
+ * The forward pass is the same as for the standard cost.
+ */
+enum { PS_M = 64 };
+
+int oracle_solve_gen(int n, int m, int p, int pT, int64_t T, uint32_t per_step,
+                     const double *F, const double *c, const double *L, const double *H,
+                     const double *X, const double *U, const double *r,
+                     const double *HT, const double *XT, const double *rT, const double *x0,
+                     const double *M, const double *s,
+                     double *S, double *v, double *K, double *d, double *x, double *u) {
+    if (n < 1 || m < 1 || p < 1 || pT < 1 || T < 1) return OR_EINVAL;
+    if (!F || !L || !H || !X || !U || !r || !HT || !XT || !rT || !x0 || !M) return OR_EINVAL;
+    if (!S || !v || !K || !d || !x || !u) return OR_EINVAL;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m, pn = (size_t)p * n;
+    const size_t pp = (size_t)p * p, mm_ = (size_t)m * m, pm = (size_t)p * m;
+    int rc = OR_OK;
+    const int pq = p > pT ? p : pT;
+    double *XH = malloc(sizeof(double) * (size_t)pq * n), *Xr = malloc(sizeof(double) * (size_t)pq);
+    double *SF = malloc(sizeof(double) * nn), *SL = malloc(sizeof(double) * nm);
+    double *Aq = malloc(sizeof(double) * nn), *Bq = malloc(sizeof(double) * nm);
+    double *W = malloc(sizeof(double) * mm_), *HM = malloc(sizeof(double) * nm);
+    double *Sc = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
+    double *av = malloc(sizeof(double) * n), *bv = malloc(sizeof(double) * m);
+    double *tm = malloc(sizeof(double) * m), *tn = malloc(sizeof(double) * n);
+    double *BK = malloc(sizeof(double) * nn), *t1 = malloc(sizeof(double) * n), *t2 = malloc(sizeof(double) * n);
+    if (!XH || !Xr || !SF || !SL || !Aq || !Bq || !W || !HM || !Sc || !w || !av || !bv || !tm || !tn || !BK ||
+        !t1 || !t2) {
+        rc = OR_EINVAL;
+        goto done;
+    }
+    double *ST = S + (size_t)T * nn, *vT = v + (size_t)T * n;
+    mm(pT, pT, n, XT, HT, XH);
+    mtm(n, pT, n, HT, XH, ST);
+    mv(pT, pT, XT, rT, Xr);
+    mtv(pT, n, HT, Xr, vT);
+    symmetrize(n, ST);
+    for (int64_t k = T - 1; k >= 0; --k) {
+        const double *Fk = at(F, per_step, PS_F, k, nn);
+        const double *ck = c ? at(c, per_step, PS_c, k, n) : NULL;
+        const double *Lk = at(L, per_step, PS_L, k, nm);
+        const double *Hk = at(H, per_step, PS_H, k, pn);
+        const double *Xk = at(X, per_step, PS_X, k, pp);
+        const double *Uk = at(U, per_step, PS_U, k, mm_);
+        const double *Mk = at(M, per_step, PS_M, k, pm);
+        const double *rk = r + (size_t)k * p;
+        const double *S1 = S + (size_t)(k + 1) * nn, *v1 = v + (size_t)(k + 1) * n;
+        double *Sk = S + (size_t)k * nn, *vk = v + (size_t)k * n;
+        double *Kk = K + (size_t)k * m * n, *dk = d + (size_t)k * m;
+        /* Aq = H^T X H + F^T S F */
+        mm(p, p, n, Xk, Hk, XH);
+        mtm(n, p, n, Hk, XH, Aq);
+        mm(n, n, n, S1, Fk, SF);
+        mtm(n, n, n, Fk, SF, BK);
+        for (size_t i = 0; i < nn; ++i) Aq[i] += BK[i];
+        /* Bq = H^T M + F^T S L */
+        mtm(n, p, m, Hk, Mk, HM);
+        mm(n, n, m, S1, Lk, SL);
+        mtm(n, n, m, Fk, SL, Bq);
+        for (size_t i = 0; i < nm; ++i) Bq[i] += HM[i];
+        /* W = U + L^T S L */
+        mtm(m, n, m, Lk, SL, W);
+        for (size_t i = 0; i < mm_; ++i) W[i] += Uk[i];
+        /* w = v - S c */
+        if (ck) mv(n, n, S1, ck, Sc); else memset(Sc, 0, sizeof(double) * n);
+        for (int i = 0; i < n; ++i) w[i] = v1[i] - Sc[i];
+        /* a = H^T X r + H^T M s + F^T w ;  b = M^T r + U s + L^T w */
+        mv(p, p, Xk, rk, Xr);
+        mtv(p, n, Hk, Xr, av);
+        mtv(n, n, Fk, w, tn);
+        for (int i = 0; i < n; ++i) av[i] += tn[i];
+        mtv(p, m, Mk, rk, bv);
+        mtv(n, m, Lk, w, tm);
+        for (int i = 0; i < m; ++i) bv[i] += tm[i];
+        if (s) {
+            const double *sk = s + (size_t)k * m;
+            mv(n, m, HM, sk, tn);
+            for (int i = 0; i < n; ++i) av[i] += tn[i];
+            mv(m, m, Uk, sk, tm);
+            for (int i = 0; i < m; ++i) bv[i] += tm[i];
+        }
+        /* K = W^{-1} Bq^T ; d = W^{-1} b */
+        rc = cholesky(m, W);
+        if (rc) goto done;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) Kk[i * n + j] = Bq[j * m + i];
+        chol_solve(m, n, W, Kk);
+        memcpy(dk, bv, sizeof(double) * m);
+        chol_solve(m, 1, W, dk);
+        /* S_k = Aq - Bq K ; v_k = a - Bq d */
+        mm(n, m, n, Bq, Kk, BK);
+        for (size_t i = 0; i < nn; ++i) Sk[i] = Aq[i] - BK[i];
+        symmetrize(n, Sk);
+        mv(n, m, Bq, dk, tn);
+        for (int i = 0; i < n; ++i) vk[i] = av[i] - tn[i];
+    }
+    memcpy(x, x0, sizeof(double) * n);
+    for (int64_t k = 0; k < T; ++k) {
+        const double *Fk = at(F, per_step, PS_F, k, nn);
+        const double *ck = c ? at(c, per_step, PS_c, k, n) : NULL;
+        const double *Lk = at(L, per_step, PS_L, k, nm);
+        const double *xk = x + (size_t)k * n;
+        double *uk = u + (size_t)k * m, *xn = x + (size_t)(k + 1) * n;
+        mv(m, n, K + (size_t)k * m * n, xk, uk);
+        for (int i = 0; i < m; ++i) uk[i] = -uk[i] + d[(size_t)k * m + i];
+        mv(n, n, Fk, xk, t1);
+        mv(n, m, Lk, uk, t2);
+        for (int i = 0; i < n; ++i) xn[i] = t1[i] + t2[i] + (ck ? ck[i] : 0.0);
+    }
+    if (!all_finite((size_t)(T + 1) * nn, S) || !all_finite((size_t)(T + 1) * n, x)) rc = OR_ENONFINITE;
+done:
+    free(XH); free(Xr); free(SF); free(SL); free(Aq); free(Bq); free(W); free(HM); free(Sc); free(w);
+    free(av); free(bv); free(tm); free(tn); free(BK); free(t1); free(t2);
     return rc;
 }
 

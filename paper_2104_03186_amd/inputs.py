@@ -39,6 +39,7 @@ import numpy as np
 BASE_SEED = 2104
 
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
+PS_M = 64  # cross term of the generalised stage cost
 
 
 @dataclasses.dataclass
@@ -65,6 +66,9 @@ class LQTProblem:
     XT: np.ndarray
     rT: np.ndarray
     x0: np.ndarray
+    # generalised stage cost (cross term and control reference); None: absent
+    M: Optional[np.ndarray] = None   # [p][m] (or [T][p][m] with PS_M)
+    s: Optional[np.ndarray] = None   # [T][m]
 
     @property
     def steps(self) -> int:
@@ -202,3 +206,25 @@ def random_problem(n: int, m: int, T: int, seed: int, p: Optional[int] = None, p
         per_step &= ~PS_c
     return LQTProblem(n=n, m=m, p=p, pT=pT, T=T, per_step=per_step, F=F, c=c, L=L, H=H, X=X, U=U,
                       r=r, HT=HT, XT=XT, rT=rT, x0=x0)
+
+
+def generalised_problem(n: int, m: int, T: int, seed: int, p: Optional[int] = None, per_step: int = 0,
+                        with_c: bool = True, with_s: bool = True, scale: float = 0.95) -> LQTProblem:
+    """random_problem with the generalised stage cost of the extension to more
+    general cost functions: a cross term M ([p][m]) between the output error
+    and the control error, and a control reference s ([T][m]).  X, M and U
+    are the blocks of one random positive definite (p + m) x (p + m) matrix,
+    so the stage cost stays convex; per_step bits F, c and r-like data only
+    (the library's transformation keeps L, H, X, U, M time-invariant)."""
+    base = random_problem(n, m, T, seed=seed, p=p, pT=n, per_step=per_step & (PS_F | PS_c), with_c=with_c,
+                          scale=scale)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, 98, seed])))
+    q = base.p + m
+    Wb = rng.normal(0.0, 1.0 / math.sqrt(q), size=(q, q))
+    Bm = Wb @ Wb.T + 0.3 * np.eye(q)
+    Bm = 0.5 * (Bm + Bm.T)
+    base.X = np.ascontiguousarray(Bm[:base.p, :base.p])
+    base.M = np.ascontiguousarray(Bm[:base.p, base.p:])
+    base.U = np.ascontiguousarray(Bm[base.p:, base.p:])
+    base.s = np.ascontiguousarray(rng.normal(0.0, 0.3, size=(T, m))) if with_s else None
+    return base

@@ -43,11 +43,22 @@ def kkt_subproblem(prob, k0, xi):
     def us(k):
         return slice(nxv + m * (k - k0), nxv + m * (k - k0 + 1))
 
+    M = getattr(prob, "M", None)
+    s = getattr(prob, "s", None)
     for k in range(k0, T):
         H, X, U = _mat(prob, "H", 8, k), _mat(prob, "X", 16, k), _mat(prob, "U", 32, k)
         P[xs(k), xs(k)] += H.T @ X @ H
         q[xs(k)] += -H.T @ X @ prob.r[k]
         P[us(k), us(k)] += U
+        # generalised stage cost: (H x - r)^T M (u - s) + 1/2 (u - s)^T U (u - s)
+        sk = np.zeros(m) if s is None else s[k]
+        if M is not None:
+            Mk = _mat(prob, "M", 64, k)
+            P[xs(k), us(k)] += H.T @ Mk
+            P[us(k), xs(k)] += Mk.T @ H
+            q[xs(k)] += -H.T @ Mk @ sk
+            q[us(k)] += -Mk.T @ prob.r[k]
+        q[us(k)] += -U @ sk
     P[xs(T), xs(T)] += prob.HT.T @ prob.XT @ prob.HT
     q[xs(T)] += -prob.HT.T @ prob.XT @ prob.rT
 
