@@ -81,6 +81,10 @@ def stage_bytes_per_step(stage, n, m, p, osz=8):
         return 8 * p
     if stage == "m2_final":    # reads r_k, S_k, v_k, K_k, d_k, writes x_k, u_k
         return 8 * p + osz * (n * n + n + m * n + m + n + m)
+    if stage == "gen_transform":  # reads r_k, s_k, writes c~_k
+        return 8 * (p + m + n)
+    if stage == "gen_post":    # reads r_k, s_k, x_k; updates K_k, d_k, u_k in place
+        return 8 * (p + m) + osz * (n + 2 * (m * n + m + m))
     return 0
 
 
@@ -99,11 +103,17 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajectory="maps"):
+def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajectory="maps", cost="standard"):
     """One instance n=4, m=2, T=args.T.  Returns the result dict.  trajectory:
-    the forward pass (closed-loop maps, or forward prefixes of the elements)."""
+    the forward pass (closed-loop maps, or forward prefixes of the elements).
+    cost: "standard" (the tracking workload), or "generalised" (a random
+    instance with the cross term M and control reference s of Section IV-D,
+    four tracked outputs)."""
     n, m, T = 4, 2, args.T
-    prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
+    if cost == "generalised":
+        prob = inputs.generalised_problem(n, m, T, seed=1, p=4)
+    else:
+        prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
     osz = 8 if prec == "fp64" else 4
     plan = api.Plan(n, m, prec=prec, device=0, max_steps=T, trajectory=trajectory)
     dp = api.DeviceProblem(prob)
@@ -391,6 +401,9 @@ def main():
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
                     help="forward pass of a --workload single run: closed-loop maps or forward prefixes")
+    ap.add_argument("--cost", choices=("standard", "generalised"), default="standard",
+                    help="--workload single: stage cost of the instance (generalised: cross term M and control "
+                         "reference s)")
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
@@ -425,7 +438,8 @@ def main():
         return
     prec = args.prec or "fp64"
     main_res = run_single(args, api, inputs, torch, prec, args.steps, args.warmup, not args.no_cpu_baseline,
-                          trajectory=args.trajectory if args.workload == "single" else "maps")
+                          trajectory=args.trajectory if args.workload == "single" else "maps",
+                          cost=args.cost if args.workload == "single" else "standard")
     out = {
         "metric": "LQT time-steps solved/s (single long instance, parallel scan)",
         "value": round(main_res["value"], 1),
@@ -440,7 +454,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f64 arithmetic, f32 results",
         "data": "synthetic (seeded generators: sinusoid-reference tracking; diagonal-cost random-walk batches)",
         "config": {"workload": f"single LQT instance nx=4 nu=2 T={args.T} {prec}"
-                               + (", trajectory by forward prefixes" if args.trajectory == "prefix" else ""),
+                               + (", trajectory by forward prefixes" if args.trajectory == "prefix" else "")
+                               + (", generalised cost (M, s)" if args.cost == "generalised" else ""),
                    "nx": 4, "nu": 2, "T": args.T, "precision": prec},
         "status": main_res["status"],
         "rel_err": main_res["rel_err"],
@@ -455,6 +470,9 @@ def main():
         m2 = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, trajectory="prefix")
         out["single_fp64_forward_prefixes"] = {k: m2[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                   "stages_avg_ms")}
+        gen = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, cost="generalised")
+        out["single_fp64_generalised_cost"] = {k: gen[k] for k in ("value", "ms_per_step", "status", "rel_err",
+                                                                   "stages_avg_ms")}
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
         out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")

@@ -116,6 +116,19 @@ typedef struct {
     const double *XT;     /* [pT][pT] terminal weight, symmetric PSD                */
     const double *rT;     /* [pT]     terminal reference r_T                        */
     const double *x0;     /* [n]      initial state                                 */
+    /* Generalised stage cost (Section IV-D): with M or s given, the running
+     * cost is 1/2 (H x - r)^T X (H x - r) + (H x - r)^T M (u - s)
+     * + 1/2 (u - s)^T U (u - s), the joint weight [X M; M^T U] symmetric PSD
+     * and U PD.  Both NULL: the cost above (M = 0, s = 0).  The library
+     * transforms the instance to the standard form (Z = U^{-1} M^T:
+     * F - L Z H, c_k + L Z r_k + L s_k, X - M Z), solves it and maps the
+     * results back (K_k + Z H, d_k + Z r_k + s_k, u_k - Z (H x_k - r_k) + s_k;
+     * S, v and x are those of the transformed instance).  It needs L, H, X
+     * and U shared by every step (LQT_ENOTSUP otherwise) and takes T n
+     * (plus T n^2 with per-step F, plus (T + 1) n when u is taken without x)
+     * doubles of extra workspace per instance. */
+    const double *M;      /* [p][m]   cross weight; NULL means M = 0                */
+    const double *s;      /* [T][m]   control reference s_0..s_{T-1}; NULL means 0  */
 } lqt_problem;
 
 /* Outputs of one instance.  Element type is double for LQT_PREC_FP64 and

@@ -30,7 +30,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("ny", ctypes.c_int32), ("nyT", ctypes.c_int32),
                 ("T", ctypes.c_int64), ("per_step", ctypes.c_uint32),
                 ("F", _vp), ("c", _vp), ("L", _vp), ("H", _vp), ("X", _vp), ("U", _vp), ("r", _vp),
-                ("HT", _vp), ("XT", _vp), ("rT", _vp), ("x0", _vp)]
+                ("HT", _vp), ("XT", _vp), ("rT", _vp), ("x0", _vp), ("M", _vp), ("s", _vp)]
 
 
 class Outputs(ctypes.Structure):

@@ -25,14 +25,14 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 class DeviceProblem:
     """An LQT instance resident in device memory (float64 tensors)."""
 
-    FIELDS = ("F", "c", "L", "H", "X", "U", "r", "HT", "XT", "rT", "x0")
+    FIELDS = ("F", "c", "L", "H", "X", "U", "r", "HT", "XT", "rT", "x0", "M", "s")
 
     def __init__(self, prob, device="cuda:0"):
         self.n, self.m, self.p, self.pT = int(prob.n), int(prob.m), int(prob.p), int(prob.pT)
         self.T, self.per_step = int(prob.T), int(prob.per_step)
         self.t = {}
         for f in self.FIELDS:
-            a = getattr(prob, f)
+            a = getattr(prob, f, None)  # M, s: generalised stage cost (Section IV-D)
             self.t[f] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
 
     def struct(self) -> _lib.Problem:

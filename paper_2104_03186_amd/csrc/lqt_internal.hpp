@@ -94,4 +94,24 @@ struct SideStream {
 };
 hipError_t small_solve(const SmallArgs& a, hipStream_t s, const StageHook* hook, const SideStream* side = nullptr);
 
+// Generalised stage cost (Section IV-D): one instance's transform to the
+// standard form and the map of its gains and controls back.  Inputs are the
+// instance's device arrays (L, H, X, U, M time-invariant; F and c as in the
+// problem); Z .. ct are workspace (gen_layout); K, d, u, x are the solve's
+// outputs (double, or float when f32 is set; any of K, d, u may be null).
+struct GenArgs {
+    const double *F, *c, *L, *H, *X, *U, *M, *r, *s;
+    int64_t T;
+    int32_t n, m, p;
+    uint32_t per_step;
+    double *Z, *ZH, *LZ, *Xt, *Ft, *ct;
+    void *K, *d, *u;
+    const void* x;
+    int32_t f32;
+};
+size_t gen_ws_doubles(int n, int m, int p, int64_t T, bool f_per_step);
+void gen_layout(GenArgs& g, double* ws);
+hipError_t gen_transform(const GenArgs& g, hipStream_t s);
+hipError_t gen_post(const GenArgs& g, hipStream_t s);
+
 }  // namespace lqt

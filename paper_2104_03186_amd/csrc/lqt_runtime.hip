@@ -277,15 +277,43 @@ size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
     return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
 }
 
-// Device bytes of one launch group: the small-path instances run one after
-// another in one region (the largest), each wavefront-path instance has its
-// own region, then the instance table.
+// Generalised stage cost (Section IV-D): an instance with M or s is solved as
+// its standard-form transform, whose c~ varies per step.
+bool is_gen(const lqt_problem& p) { return p.M || p.s; }
+
+// Shape of the standard-form instance a generalised one is solved as (the
+// sizes depend on the presence of c, not on its values).
+lqt_problem std_shape(const lqt_problem& p) {
+    if (!is_gen(p)) return p;
+    lqt_problem q = p;
+    q.per_step |= LQT_PS_c;
+    if (!q.c) q.c = p.r;
+    q.M = nullptr;
+    q.s = nullptr;
+    return q;
+}
+
+// Transform workspace of a generalised instance, and the state scratch of
+// the control map when the caller takes u without x.
+size_t gen_bytes(const lqt_problem& p, const lqt_outputs& o) {
+    if (!is_gen(p)) return 0;
+    size_t b = align_up(lqt::gen_ws_doubles(p.nx, p.nu, p.ny, p.T, p.per_step & LQT_PS_F) * sizeof(double));
+    if (o.u && !o.x) b += align_up((size_t)(p.T + 1) * p.nx * sizeof(double));
+    return b;
+}
+
+// Device bytes of one launch group: the transform regions of generalised
+// instances, then the small-path instances, which run one after another in
+// one region (the largest), each wavefront-path instance's own region, then
+// the instance table.
 struct BatchSize {
     lqt_plan_t plan = nullptr;
-    size_t small = 0, wave = 0;
+    size_t gen = 0, small = 0, wave = 0;
     size_t nwave = 0;
     explicit BatchSize(lqt_plan_t pl) : plan(pl) {}
-    void add(const lqt_problem& p, const lqt_outputs& o) {
+    void add(const lqt_problem& p0, const lqt_outputs& o) {
+        gen += gen_bytes(p0, o);
+        const lqt_problem p = std_shape(p0);
         if (path_of(p) == Path::Small) {
             const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && (o.x || o.u);
             small = std::max(small, align_up(layout_for(p, !o.K, !o.d, m2, !o.S, !o.v).total));
@@ -294,7 +322,7 @@ struct BatchSize {
             ++nwave;
         }
     }
-    size_t total() const { return small + (nwave ? wave + align_up(nwave * sizeof(lqt::GInst)) : 0); }
+    size_t total() const { return gen + small + (nwave ? wave + align_up(nwave * sizeof(lqt::GInst)) : 0); }
 };
 
 lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, int idx) {
@@ -324,6 +352,10 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
         }
     }
     if (p.per_step & ~63u) return fail(plan, LQT_EINVAL, "instance %d: unknown per_step bits 0x%x", idx, p.per_step);
+    if (is_gen(p) && (p.per_step & (LQT_PS_L | LQT_PS_H | LQT_PS_X | LQT_PS_U)))
+        return fail(plan, LQT_ENOTSUP,
+                    "instance %d: with M or s (generalised cost) only F and c may vary per step (per_step=0x%x)", idx,
+                    p.per_step);
     if (!p.F || !p.L || !p.H || !p.X || !p.U || !p.r || !p.HT || !p.XT || !p.rT || !p.x0)
         return fail(plan, LQT_EINVAL, "instance %d: a required input pointer is NULL", idx);
     if ((p.per_step & LQT_PS_c) && !p.c)
@@ -411,24 +443,73 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         return 4 * tile_class_of(probs[i]) + (e == 0 ? 0 : (e == lqt::kEng32m16 ? 2 : 1));
     };
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
-    // workspace: [small-path region (largest small instance)] [wave region] [instance table]
+    // workspace: [generalised-cost transforms] [small-path region (largest small instance)] [wave region]
+    // [instance table]
     BatchSize bs(plan);
     for (int i = 0; i < count; ++i) bs.add(probs[i], outs[i]);
     std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
     size_t wave_need = 0;
     for (size_t j = 0; j < wave.size(); ++j) {
         ws_off[j] = (int64_t)wave_need;
-        wave_need += wave_bytes(plan, probs[wave[j]]);
+        wave_need += wave_bytes(plan, std_shape(probs[wave[j]]));
         kd_off[j] = (int64_t)wave_need;
         wave_need += wave_kd_bytes(probs[wave[j]], outs[wave[j]]);
     }
     lqt_status st = ensure_ws(plan, A, bs.total());
     if (st != LQT_OK) return st;
+    // generalised instances: transform to the standard form (Section IV-D) at
+    // the start of the arena, solve the transforms, map the results back
+    std::vector<lqt_problem> tp;
+    std::vector<lqt_outputs> to;
+    std::vector<lqt::GenArgs> gens;
+    if (bs.gen) {
+        tp.assign(probs, probs + count);
+        to.assign(outs, outs + count);
+        size_t off = 0;
+        if (plan->prof.on) Profiler::begin(&plan->prof, "gen_transform", s);
+        for (int i = 0; i < count; ++i) {
+            const lqt_problem& p = probs[i];
+            if (!is_gen(p)) continue;
+            lqt::GenArgs g{};
+            g.F = p.F; g.c = p.c; g.L = p.L; g.H = p.H; g.X = p.X; g.U = p.U; g.M = p.M; g.r = p.r; g.s = p.s;
+            g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny;
+            g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+            lqt::gen_layout(g, (double*)(A.ws + off));
+            off += align_up(lqt::gen_ws_doubles(p.nx, p.nu, p.ny, p.T, p.per_step & LQT_PS_F) * sizeof(double));
+            if (outs[i].u && !outs[i].x) {
+                to[i].x = A.ws + off;
+                off += align_up((size_t)(p.T + 1) * p.nx * sizeof(double));
+            }
+            g.K = to[i].K; g.d = to[i].d; g.u = to[i].u; g.x = to[i].x;
+            g.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
+            tp[i].F = g.Ft; tp[i].c = g.ct; tp[i].X = g.Xt;
+            tp[i].per_step |= LQT_PS_c;
+            tp[i].M = nullptr;
+            tp[i].s = nullptr;
+            hipError_t e = lqt::gen_transform(g, s);
+            if (e != hipSuccess) return fail(plan, LQT_EHIP, "transform launch failed: %s", hipGetErrorString(e));
+            gens.push_back(g);
+        }
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        probs = tp.data();
+        outs = to.data();
+    }
+    auto post = [&]() -> lqt_status {
+        if (gens.empty()) return LQT_OK;
+        if (plan->prof.on) Profiler::begin(&plan->prof, "gen_post", s);
+        for (const lqt::GenArgs& g : gens) {
+            hipError_t e = lqt::gen_post(g, s);
+            if (e != hipSuccess) return fail(plan, LQT_EHIP, "map-back launch failed: %s", hipGetErrorString(e));
+        }
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        return LQT_OK;
+    };
+    char* const base = A.ws + bs.gen;
     for (int i : small) {
-        st = launch_one(plan, A.ws, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
+        st = launch_one(plan, base, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
         if (st != LQT_OK) return st;
     }
-    if (wave.empty()) return LQT_OK;
+    if (wave.empty()) return post();
     if (A.ginst_cap < wave.size()) {
         if (A.ginst_done) (void)hipEventSynchronize(A.ginst_done);
         if (A.ginst_host) (void)hipHostFree(A.ginst_host);
@@ -441,7 +522,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     } else if (A.ginst_done) {
         (void)hipEventSynchronize(A.ginst_done);  // previous upload has left the buffer
     }
-    char* wbase = A.ws + bs.small;
+    char* wbase = base + bs.small;
     std::vector<char> want_fwd_c(wave.size(), 0);
     int64_t chunk0 = 0;
     for (size_t j = 0; j < wave.size(); ++j) {
@@ -495,7 +576,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
         j0 = j1;
     }
-    return LQT_OK;
+    return post();
 }
 
 void arena_release(Arena& A) {

@@ -54,7 +54,7 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
 
 STRUCTS = {
     "lqt_problem": ("Problem", ["nx", "nu", "ny", "nyT", "T", "per_step", "F", "c", "L", "H", "X", "U", "r", "HT",
-                                "XT", "rT", "x0"]),
+                                "XT", "rT", "x0", "M", "s"]),
     "lqt_outputs": ("Outputs", ["S", "v", "K", "d", "x", "u", "status"]),
     "lqt_plan_desc": ("PlanDesc", ["device", "max_nx", "max_nu", "prec", "hbm_budget_bytes", "max_steps",
                                    "max_inflight", "trajectory"]),
