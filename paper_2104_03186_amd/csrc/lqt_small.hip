@@ -231,8 +231,10 @@ LQT_DI void load_invariant(const SmallArgs& a, Step<N, M>& st) {
 }
 
 // Step data modes: time-invariant with square H, X (the reference row feeds
-// eta directly), time-invariant general, per-step (time-varying).
-enum Mode { kFast = 0, kInv = 1, kVar = 2 };
+// eta directly), time-invariant general, per-step (time-varying), and
+// time-invariant except the offsets c_k (constants of the invariant mode,
+// c_k read per step; e.g. the standard form of the generalised cost).
+enum Mode { kFast = 0, kInv = 1, kVar = 2, kInvC = 3 };
 
 template <int N, int M, int MODE>
 LQT_DI void load_step(const SmallArgs& a, int64_t k, Step<N, M>& st) {
@@ -257,6 +259,7 @@ LQT_DI void load_step(const SmallArgs& a, int64_t k, Step<N, M>& st) {
             const double rq = r[q];
             LQT_UNROLL for (int i = 0; i < N; ++i) st.e[i] = fma(W[i * p + q], rq, st.e[i]);
         }
+        if constexpr (MODE == kInvC) LQT_UNROLL for (int i = 0; i < N; ++i) st.c[i] = a.c[k * N + i];
     }
 }
 
@@ -707,7 +710,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(SmallArgs a) {
                 LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = inv.F[i];
                 LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = inv.L[i];
                 LQT_UNROLL for (int i = 0; i < M * M; ++i) U[i] = inv.U[i];
-                LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = inv.c[i];
+                if constexpr (MODE == kInvC) LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = a.c[k * N + i];
+                else LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = inv.c[i];
                 LQT_UNROLL for (int i = 0; i < S::size; ++i) Js[i] = inv.J[i];
                 if constexpr (MODE == kFast) {
                     eta_sq<N>(inv.W, rr, e);
@@ -1107,7 +1111,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_final(SmallArgs a) {
         } else {
             LQT_UNROLL for (int i = 0; i < N * N; ++i) F[i] = F0[i];
             LQT_UNROLL for (int i = 0; i < N * M; ++i) L[i] = L0[i];
-            LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = c0[i];
+            if constexpr (MODE == kInvC) LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = a.c[k * N + i];
+            else LQT_UNROLL for (int i = 0; i < N; ++i) cc[i] = c0[i];
         }
         double u[M];
         LQT_UNROLL for (int q = 0; q < M; ++q) {
@@ -1433,7 +1438,7 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h, cons
             k_fwd_top<N><<<1, kBlock, 0, s>>>(a);
         }
         Stage st(h, "fwd_final", s);
-        const bool regs = MODE != kVar && all && even;
+        const bool regs = (MODE == kFast || MODE == kInv) && all && even;
         bool fdone = false;
         if constexpr (N % 2 == 0 && M % 2 == 0) {
             // gain rows of the whole chunk in registers: up to 128 values
@@ -1455,8 +1460,9 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h, cons
 
 template <int N, int M, typename OT>
 static void run_typed(const SmallArgs& a, hipStream_t s, const StageHook* h, const SideStream* side) {
-    const bool var = (a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U)) != 0;
-    if (var) run_mode<N, M, kVar, OT>(a, s, h, side);
+    const uint32_t ps = a.per_step & (kPS_F | kPS_c | kPS_L | kPS_H | kPS_X | kPS_U);
+    if (ps == kPS_c) run_mode<N, M, kInvC, OT>(a, s, h, side);
+    else if (ps) run_mode<N, M, kVar, OT>(a, s, h, side);
     else if (a.p == N) run_mode<N, M, kFast, OT>(a, s, h, side);
     else run_mode<N, M, kInv, OT>(a, s, h, side);
 }

@@ -113,7 +113,7 @@ def test_top_level_blocks(api, plan, T, chunk):
     assert_parity(do.host(), oracle.solve(prob))
 
 
-@pytest.mark.parametrize("per_step", [0, 1 | 2 | 4 | 8 | 16 | 32, 1 | 8])
+@pytest.mark.parametrize("per_step", [0, 1 | 2 | 4 | 8 | 16 | 32, 1 | 8, 2])
 @pytest.mark.parametrize("nm", DIMS)
 def test_random_problems(api, plan, nm, per_step):
     n, m = nm
