@@ -228,3 +228,74 @@ def generalised_problem(n: int, m: int, T: int, seed: int, p: Optional[int] = No
     base.U = np.ascontiguousarray(Bm[base.p:, base.p:])
     base.s = np.ascontiguousarray(rng.normal(0.0, 0.3, size=(T, m))) if with_s else None
     return base
+
+
+@dataclasses.dataclass
+class UnicycleProblem:
+    """Nonlinear tracking with the unicycle model of the nonlinear experiment
+    (Section VI): state (p_x, p_y, theta, speed), control (acceleration, turn
+    rate), x_{k+1} = f(x_k, u_k; dt_k); running cost
+    1/2 (H x - r_k)^T X_k (H x - r_k) + 1/2 u^T U u, terminal
+    1/2 (H_T x - r_T)^T X_T (H_T x - r_T).  X carries a time axis (weights
+    switch on at the steps with a reference point).  ``xbar``, ``ubar``: the
+    nominal trajectory the iteration starts from."""
+    T: int
+    dt: np.ndarray     # [T]
+    H: np.ndarray      # [3][4]
+    X: np.ndarray      # [T][3][3]
+    U: np.ndarray      # [2][2]
+    r: np.ndarray      # [T][3]
+    HT: np.ndarray     # [3][4]
+    XT: np.ndarray     # [3][3]
+    rT: np.ndarray     # [3]
+    x0: np.ndarray     # [4]
+    xbar: np.ndarray   # [T + 1][4]
+    ubar: np.ndarray   # [T][2]
+    n: int = 4
+    m: int = 2
+    p: int = 3
+
+
+def race_track(T: int, dt: float = 0.1, omega: float = 0.12):
+    """A closed synthetic track (the paper's track is shown only in a figure):
+    P(phi) = (50 cos phi, 30 sin phi + 8 sin 2 phi), phi = omega t, driven
+    round several times.  Returns positions [T+1][2], unwrapped heading
+    [T+1] and speed [T+1] along it."""
+    t = dt * np.arange(T + 1, dtype=np.float64)
+    ph = omega * t
+    pos = np.stack([50.0 * np.cos(ph), 30.0 * np.sin(ph) + 8.0 * np.sin(2.0 * ph)], axis=1)
+    vel = omega * np.stack([-50.0 * np.sin(ph), 30.0 * np.cos(ph) + 16.0 * np.cos(2.0 * ph)], axis=1)
+    heading = np.unwrap(np.arctan2(vel[:, 1], vel[:, 0]))
+    speed = np.hypot(vel[:, 0], vel[:, 1])
+    return pos, heading, speed
+
+
+def unicycle_problem(T: int, seed: int = 0, ref_every: int = 5, dt: float = 0.1, noise: float = 0.5,
+                     start: str = "track") -> UnicycleProblem:
+    """Nonlinear unicycle tracking workload (Section VI, nonlinear experiment)
+    on the synthetic race track: reference points (position and heading,
+    jittered by N(0, noise^2) in position) every ``ref_every`` steps with the
+    experiment's weights (100 on position, 1000 on heading; 1e-6 elsewhere and
+    at the terminal step), U = diag(1, 100), dt = 0.1.  start = "track": the
+    nominal trajectory is the noiseless track with zero controls; "x0": every
+    nominal state is x_0 (one of the paper's suggested initialisations)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, 7, seed])))
+    pos, heading, speed = race_track(T, dt)
+    r = np.concatenate([pos[:T] + rng.normal(0.0, noise, size=(T, 2)), heading[:T, None]], axis=1)
+    has = (np.arange(T) % ref_every) == 0
+    lo = 1e-6
+    X = np.empty((T, 3, 3))
+    X[:] = lo * np.eye(3)
+    X[has] = np.diag([100.0, 100.0, 1000.0])
+    H = np.zeros((3, 4))
+    H[0, 0] = H[1, 1] = H[2, 2] = 1.0
+    x0 = np.array([pos[0, 0], pos[0, 1], heading[0], speed[0]])
+    if start == "track":
+        xbar = np.concatenate([pos, heading[:, None], speed[:, None]], axis=1)
+    else:
+        xbar = np.broadcast_to(x0, (T + 1, 4)).copy()
+    xbar[0] = x0
+    return UnicycleProblem(T=T, dt=np.full(T, dt), H=H, X=np.ascontiguousarray(X), U=np.diag([1.0, 100.0]),
+                           r=np.ascontiguousarray(r), HT=H.copy(), XT=lo * np.eye(3),
+                           rT=np.array([pos[T, 0], pos[T, 1], heading[T]]), x0=x0,
+                           xbar=np.ascontiguousarray(xbar), ubar=np.zeros((T, 2)))

@@ -1,0 +1,102 @@
+"""Pins of the oracle's iterated linearisation (Section IV-E) with the unicycle
+model of the nonlinear experiment (Section VI).  CPU only.
+
+* the hand-written Jacobians against central finite differences of the
+  model;
+* the linearised model reproduces f at the expansion point and its error
+  shrinks quadratically with the distance from it (a wrong offset c_k or
+  Jacobian entry breaks one of the two);
+* a converged iterate is a solution of the nonlinear problem: dynamically
+  feasible (rollout of its controls through f gives its states) and
+  stationary (the directional derivatives of the nonlinear total cost,
+  by finite differences of an independent rollout, vanish), unlike the
+  first iterate;
+* on a short horizon, a general-purpose minimiser of the nonlinear cost
+  over the controls (scipy BFGS) reaches the same cost and controls.
+"""
+import numpy as np
+import pytest
+
+from oracle import iterated
+from paper_2104_03186_amd import inputs
+
+
+def test_jacobians_match_finite_differences():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        x = rng.normal(size=4) * [10, 10, 3, 4]
+        u = rng.normal(size=2)
+        dt = rng.uniform(0.01, 0.3)
+        Jx, Ju = iterated.unicycle_jacobians(x, u, dt)
+        h = 1e-6
+        for j in range(4):
+            e = np.zeros(4)
+            e[j] = h
+            fd = (iterated.unicycle_f(x + e, u, dt) - iterated.unicycle_f(x - e, u, dt)) / (2 * h)
+            assert np.allclose(Jx[:, j], fd, atol=1e-8, rtol=1e-7)
+        for j in range(2):
+            e = np.zeros(2)
+            e[j] = h
+            fd = (iterated.unicycle_f(x, u + e, dt) - iterated.unicycle_f(x, u - e, dt)) / (2 * h)
+            assert np.allclose(Ju[:, j], fd, atol=1e-8, rtol=1e-7)
+
+
+def test_linearised_model_is_first_order_taylor():
+    prob = inputs.unicycle_problem(30, seed=1)
+    rng = np.random.default_rng(4)
+    xbar = prob.xbar + rng.normal(scale=0.3, size=prob.xbar.shape)
+    ubar = rng.normal(scale=0.5, size=prob.ubar.shape)
+    lin = iterated.linearise(prob, xbar, ubar)
+    for k in (0, 7, 29):
+        f0 = iterated.unicycle_f(xbar[k], ubar[k], prob.dt[k])
+        assert np.allclose(lin.F[k] @ xbar[k] + lin.c[k] + lin.L[k] @ ubar[k], f0, rtol=0, atol=1e-12)
+        dx, du = rng.normal(size=4), rng.normal(size=2)
+        errs = []
+        for eps in (1e-2, 5e-3):
+            x, u = xbar[k] + eps * dx, ubar[k] + eps * du
+            errs.append(np.linalg.norm(iterated.unicycle_f(x, u, prob.dt[k]) - (lin.F[k] @ x + lin.c[k] + lin.L[k] @ u)))
+        assert 3.0 < errs[0] / errs[1] < 5.0, errs  # second-order remainder
+
+
+def _directional_derivatives(prob, u, ndir=6, h=1e-5):
+    rng = np.random.default_rng(11)
+    out = []
+    for _ in range(ndir):
+        d = rng.normal(size=u.shape)
+        d /= np.linalg.norm(d)
+        out.append((iterated.nonlinear_cost(prob, u + h * d) - iterated.nonlinear_cost(prob, u - h * d)) / (2 * h))
+    return np.array(out)
+
+
+def test_converged_iterate_solves_the_nonlinear_problem():
+    prob = inputs.unicycle_problem(200, seed=2)
+    x1, u1, _ = iterated.iterate(prob, 1)
+    x, u, changes = iterated.iterate(prob, 12)
+    assert changes[-1] < 1e-10 and changes[0] > 1e-2, changes
+    # feasible: the states are the rollout of the controls through f
+    assert np.max(np.abs(iterated.rollout(prob, u) - x)) < 1e-10
+    assert np.max(np.abs(iterated.rollout(prob, u1) - x1)) > 1e-3  # the first iterate is not
+    # stationary: the gradient of the nonlinear cost vanishes at u, not at u1
+    g = _directional_derivatives(prob, u)
+    g1 = _directional_derivatives(prob, u1)
+    assert np.max(np.abs(g)) < 1e-5 * np.max(np.abs(g1)), (g, g1)
+
+
+def test_short_horizon_matches_general_minimiser():
+    from scipy.optimize import minimize
+
+    prob = inputs.unicycle_problem(12, seed=5, ref_every=3)
+    x, u, changes = iterated.iterate(prob, 15)
+    assert changes[-1] < 1e-11, changes
+    res = minimize(lambda z: iterated.nonlinear_cost(prob, z.reshape(-1, 2)), np.zeros(2 * prob.T), method="BFGS",
+                   options={"gtol": 1e-10, "maxiter": 20000})
+    j_it = iterated.nonlinear_cost(prob, u)
+    assert abs(res.fun - j_it) <= 1e-8 * abs(j_it), (res.fun, j_it)
+    assert np.max(np.abs(res.x.reshape(-1, 2) - u)) < 1e-4
+
+
+@pytest.mark.parametrize("start", ["track", "x0"])
+def test_generator_shapes(start):
+    prob = inputs.unicycle_problem(50, start=start)
+    assert prob.X.shape == (50, 3, 3) and prob.r.shape == (50, 3) and prob.xbar.shape == (51, 4)
+    assert np.array_equal(prob.xbar[0], prob.x0)
