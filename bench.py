@@ -285,6 +285,67 @@ def run_dense(args, api, inputs, torch, prec):
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
 
 
+def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
+    """Iterated linearisation (Section IV-E) on the unicycle of the nonlinear
+    experiment (Section VI): T = args.nl_T steps, args.nl_rounds rounds per
+    solve (the experiment: T = 1e5, 10 rounds), synthetic race track.  One
+    timed solve = restore the nominal trajectory (device copy) + all rounds.
+    The oracle's sequential iteration (the same rounds) is the parity
+    reference and, timed, the CPU baseline."""
+    T, rounds = args.nl_T, args.nl_rounds
+    prob = inputs.unicycle_problem(T, seed=0)
+    plan = api.Plan(4, 2, prec=prec, device=0, max_steps=T)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dp = api.DeviceNLProblem(prob)
+    x0 = torch.from_numpy(prob.xbar).to("cuda:0", dt).contiguous()
+    u0 = torch.from_numpy(prob.ubar).to("cuda:0", dt).contiguous()
+    x, u = x0.clone(), u0.clone()
+    change = torch.zeros(rounds, dtype=torch.float64, device="cuda:0")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream(0)
+
+    def one():
+        x.copy_(x0)
+        u.copy_(u0)
+        plan.nl_iterate(dp, rounds, x, u, change, status, stream)
+
+    one()
+    torch.cuda.synchronize()
+    st = int(status.item())
+    rel_err, cpu = None, None
+    if not args.no_parity or with_cpu:
+        from oracle import iterated
+
+        t0 = time.perf_counter()
+        rx, ru, rch = iterated.iterate(prob, rounds)
+        secs = time.perf_counter() - t0
+        if not args.no_parity:
+            rel_err = {"x": rel(x.double().cpu().numpy(), rx), "u": rel(u.double().cpu().numpy(), ru),
+                       "last_change_gpu": float(change[-1].item()), "last_change_oracle": rch[-1]}
+        if with_cpu:
+            cpu = {"value": round(T * rounds / secs, 1), "unit": "steps*rounds/s", "cores": 1, "kind": "oracle",
+                   "sample": f"one full sequential FP64 iteration ({rounds} rounds, T={T}; {secs:.1f} s)"}
+    plan.profile(True)
+    plan.profile_read()
+    one()
+    stages = plan.profile_read()
+    plan.profile(False)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.nl_steps):
+        one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.nl_steps
+    plan.close()
+    return {"workload": f"iterated nonlinear LQT, unicycle, T={T}, {rounds} rounds, {prec}",
+            "ms_per_solve": round(ms, 3), "ms_per_round": round(ms / rounds, 4),
+            "value": round(T * rounds / (ms / 1e3), 1), "unit": "steps*rounds/s", "status": st,
+            "rel_err": rel_err, "cpu_baseline": cpu,
+            "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+
+
 def run_copy(args, torch):
     """Plain device copy of 256 MiB (float64), three times: the calibration of
     the HBM byte counters (a copy moves exactly its size in each direction)."""
@@ -396,7 +457,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "copy"), default="all")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "nonlinear", "copy"),
+                    default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
@@ -404,6 +466,9 @@ def main():
     ap.add_argument("--cost", choices=("standard", "generalised"), default="standard",
                     help="--workload single: stage cost of the instance (generalised: cross term M and control "
                          "reference s)")
+    ap.add_argument("--nl-T", type=int, default=100_000)
+    ap.add_argument("--nl-rounds", type=int, default=10)
+    ap.add_argument("--nl-steps", type=int, default=5)
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
@@ -432,6 +497,10 @@ def main():
         return
     if args.workload == "dense":
         print(json.dumps(run_dense(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        return
+    if args.workload == "nonlinear":
+        print(json.dumps(run_nonlinear(args, api, inputs, torch, args.prec or "fp64",
+                                       not args.no_cpu_baseline)), flush=True)
         return
     if args.workload == "serving":
         print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed")), flush=True)
@@ -473,6 +542,7 @@ def main():
         gen = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, cost="generalised")
         out["single_fp64_generalised_cost"] = {k: gen[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                    "stages_avg_ms")}
+        out["nonlinear_fp64"] = run_nonlinear(args, api, inputs, torch, "fp64", not args.no_cpu_baseline)
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
         out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")

@@ -224,6 +224,47 @@ typedef struct {
 
 lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats *out);
 
+/* Iterated linearisation for nonlinear dynamics (Section IV-E): starting
+ * from a nominal trajectory (xbar, ubar), each iteration linearises the
+ * dynamics by the first-order Taylor expansion about the nominal,
+ * x_{k+1} = F_k x_k + c_k + L_k u_k with F_k = df/dx, L_k = df/du at
+ * (xbar_k, ubar_k) and c_k = f(xbar_k, ubar_k) - F_k xbar_k - L_k ubar_k,
+ * solves that LQT (the plan's scan, routing and trajectory method) and takes
+ * its optimal (x, u) as the next nominal.  Output and control maps are linear
+ * (h(x) = H x, g(u) = u); the cost is that of lqt_problem. */
+typedef enum {
+    /* Unicycle of the nonlinear experiment (Section VI): x = (p_x, p_y,
+     * theta, speed), u = (acceleration, turn rate), f(x, u) = (p_x + speed
+     * cos(theta) dt_k, p_y + speed sin(theta) dt_k, theta + turn rate dt_k,
+     * speed + acceleration dt_k); nx = 4, nu = 2. */
+    LQT_NL_UNICYCLE = 0
+} lqt_nl_model;
+
+typedef struct {
+    lqt_nl_model model;
+    int32_t ny, nyT;      /* tracked outputs at steps 0..T-1 and at T               */
+    int64_t T;
+    uint32_t per_step;    /* LQT_PS_H, LQT_PS_X, LQT_PS_U bits (as in lqt_problem)  */
+    const double *dt;     /* [T]       step lengths dt_k                            */
+    const double *H, *X, *U, *r, *HT, *XT, *rT, *x0;  /* as in lqt_problem        */
+} lqt_nl_problem;
+
+/* Run `iterations` (>= 1) linearise-and-solve rounds on `stream`
+ * (stream-ordered, asynchronous, like lqt_solve).  x ([T+1][nx]) and u
+ * ([T][nu]), device arrays of the plan's output type, hold the nominal
+ * trajectory on entry and the last round's optimal states and controls on
+ * return (the round solves from x_0 = prob->x0; xbar_0 is the first
+ * expansion point).  change (optional, device, [iterations] doubles)
+ * receives max_{k,i} |u_new - u_nominal| of each round, a convergence
+ * measure; status (optional, device int32) the first failing round's
+ * lqt_status, else LQT_OK.  Workspace: (n^2 + n m + n + m) T doubles of
+ * linearised model beside the solve's own.  Argument errors (LQT_EINVAL,
+ * nothing enqueued): unknown model, per_step bits other than H, X, U, NULL
+ * pointers, iterations < 1, the model's nx, nu above the plan's maxima, and
+ * the checks of lqt_solve on the linearised instance. */
+lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem *prob, int32_t iterations, void *x, void *u,
+                          double *change, int32_t *status, void *stream);
+
 /* Wait for all work of the plan, then release it and its workspace. */
 lqt_status lqt_destroy(lqt_plan_t plan);
 

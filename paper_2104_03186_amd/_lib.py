@@ -21,7 +21,7 @@ TRAJ_MAPS, TRAJ_PREFIX = 0, 1
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
-            "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error")
+            "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate")
 
 _vp = ctypes.c_void_p
 
@@ -31,6 +31,15 @@ class Problem(ctypes.Structure):
                 ("T", ctypes.c_int64), ("per_step", ctypes.c_uint32),
                 ("F", _vp), ("c", _vp), ("L", _vp), ("H", _vp), ("X", _vp), ("U", _vp), ("r", _vp),
                 ("HT", _vp), ("XT", _vp), ("rT", _vp), ("x0", _vp), ("M", _vp), ("s", _vp)]
+
+
+class NLProblem(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("ny", ctypes.c_int32), ("nyT", ctypes.c_int32), ("T", ctypes.c_int64),
+                ("per_step", ctypes.c_uint32), ("dt", _vp), ("H", _vp), ("X", _vp), ("U", _vp), ("r", _vp),
+                ("HT", _vp), ("XT", _vp), ("rT", _vp), ("x0", _vp)]
+
+
+NL_UNICYCLE = 0
 
 
 class Outputs(ctypes.Structure):
@@ -93,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.lqt_profile_select.restype = ctypes.c_int
     lib.lqt_profile_read.argtypes = [_vp, ctypes.POINTER(StageTime), ctypes.c_int32]
     lib.lqt_profile_read.restype = ctypes.c_int32
+    lib.lqt_nl_iterate.argtypes = [_vp, ctypes.POINTER(NLProblem), ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
+    lib.lqt_nl_iterate.restype = ctypes.c_int
     lib.lqt_last_error.argtypes = [_vp]
     lib.lqt_last_error.restype = ctypes.c_char_p
     _lib = lib

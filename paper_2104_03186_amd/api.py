@@ -43,6 +43,28 @@ class DeviceProblem:
         return s
 
 
+class DeviceNLProblem:
+    """A nonlinear tracking instance for the iterated linearisation (Section
+    IV-E) resident in device memory; ``prob`` has the attributes of
+    inputs.UnicycleProblem (model: the unicycle of Section VI)."""
+
+    FIELDS = ("dt", "H", "X", "U", "r", "HT", "XT", "rT", "x0")
+
+    def __init__(self, prob, device="cuda:0"):
+        self.T, self.p, self.pT = int(prob.T), int(prob.p), int(np.asarray(prob.rT).shape[0])
+        X = np.asarray(prob.X)
+        self.per_step = _lib.PS_X if X.ndim == 3 else 0
+        self.t = {f: torch.from_numpy(np.ascontiguousarray(getattr(prob, f), dtype=np.float64)).to(device)
+                  for f in self.FIELDS}
+
+    def struct(self) -> _lib.NLProblem:
+        s = _lib.NLProblem()
+        s.model, s.ny, s.nyT, s.T, s.per_step = _lib.NL_UNICYCLE, self.p, self.pT, self.T, self.per_step
+        for f in self.FIELDS:
+            setattr(s, f, _ptr(self.t[f]))
+        return s
+
+
 class DeviceOutputs:
     """Output buffers of one instance.  ``want`` lists the families to produce
     (the others are passed as NULL)."""
@@ -125,6 +147,28 @@ class Plan:
         for k, t in out.t.items():
             if t is not None and t.dtype != want:
                 raise TypeError(f"output {k} is {t.dtype}; a {self.prec} plan writes {want}")
+
+    def nl_iterate(self, prob: "DeviceNLProblem", iterations: int, x: torch.Tensor, u: torch.Tensor,
+                   change: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                   stream=None) -> None:
+        """Iterated linearisation (lqt_nl_iterate): x ([T+1][4]) and u ([T][2])
+        hold the nominal trajectory and receive the last round's solution;
+        change ([iterations] float64) the per-round max |u_new - u_nominal|;
+        status (int32) the first failing round's status.  Asynchronous."""
+        want = torch.float64 if self.prec == "fp64" else torch.float32
+        for name, t in (("x", x), ("u", u)):
+            if t.dtype != want or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous {want} tensor for a {self.prec} plan")
+        if change is not None and change.dtype != torch.float64:
+            raise TypeError("change must be float64")
+        if status is not None and status.dtype != torch.int32:
+            raise TypeError("status must be int32")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        ps = prob.struct()
+        _lib.check(_lib.load().lqt_nl_iterate(self._h, ctypes.byref(ps), int(iterations), _ptr(x), _ptr(u),
+                                              _ptr(change), _ptr(status), ctypes.c_void_p(stream.cuda_stream)),
+                   self._h)
 
     def submit(self, prob: DeviceProblem, out: DeviceOutputs) -> int:
         self._check_dtype(out)

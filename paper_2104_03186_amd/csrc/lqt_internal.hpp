@@ -114,4 +114,19 @@ void gen_layout(GenArgs& g, double* ws);
 hipError_t gen_transform(const GenArgs& g, hipStream_t s);
 hipError_t gen_post(const GenArgs& g, hipStream_t s);
 
+// Iterated linearisation (Section IV-E), unicycle model: one round's
+// expansion of the dynamics about the nominal (x, u: the plan's output type)
+// into per-step F, L, c, plus a double copy of the nominal controls.
+struct NlArgs {
+    const double* dt;
+    int64_t T;
+    const void *x, *u;  // nominal trajectory [T+1][4], [T][2]
+    double *F, *L, *c, *ubar;  // [T][4][4], [T][4][2], [T][4], [T][2]
+    int32_t f32;
+};
+hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipStream_t s);
+hipError_t nl_linearise(const NlArgs& g, hipStream_t s);
+hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s);
+hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s);
+
 }  // namespace lqt

@@ -1,0 +1,125 @@
+// Iterated linearisation for nonlinear dynamics (Section IV-E): the device
+// side of one round -- the first-order Taylor expansion of the dynamics about
+// the nominal trajectory, and the round's convergence measure.  Model: the
+// unicycle of the nonlinear experiment (Section VI).
+#include <hip/hip_runtime.h>
+
+#include "lqt_internal.hpp"
+
+namespace lqt {
+
+namespace {
+
+constexpr int kNlBlock = 256;
+
+// One thread per step k: F_k = df/dx, L_k = df/du at (xbar_k, ubar_k),
+// c_k = f(xbar_k, ubar_k) - F_k xbar_k - L_k ubar_k, and a double copy of
+// ubar_k for the change measure.  Unicycle, x = (p_x, p_y, theta, s),
+// u = (a, w): f = (p_x + s cos(theta) dt, p_y + s sin(theta) dt, theta + w dt,
+// s + a dt).
+template <typename OT>
+__global__ __launch_bounds__(kNlBlock) void k_nl_linearise_unicycle(NlArgs g) {
+    const int64_t k = (int64_t)blockIdx.x * kNlBlock + threadIdx.x;
+    if (k >= g.T) return;
+    const OT* xb = (const OT*)g.x + k * 4;
+    const OT* ub = (const OT*)g.u + k * 2;
+    const double px = (double)xb[0], py = (double)xb[1], th = (double)xb[2], sp = (double)xb[3];
+    const double a = (double)ub[0], w = (double)ub[1];
+    const double dt = g.dt[k];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double F[16] = {1.0, 0.0, -sp * sn * dt, cs * dt,
+                    0.0, 1.0, sp * cs * dt, sn * dt,
+                    0.0, 0.0, 1.0, 0.0,
+                    0.0, 0.0, 0.0, 1.0};
+    double L[8] = {0.0, 0.0,
+                   0.0, 0.0,
+                   0.0, dt,
+                   dt, 0.0};
+    const double fx[4] = {px + sp * cs * dt, py + sp * sn * dt, th + w * dt, sp + a * dt};
+    const double xv[4] = {px, py, th, sp};
+    const double uv[2] = {a, w};
+    double* Fo = g.F + k * 16;
+    double* Lo = g.L + k * 8;
+    double* co = g.c + k * 4;
+    for (int i = 0; i < 4; ++i) {
+        double acc = fx[i];
+        for (int j = 0; j < 4; ++j) acc -= F[i * 4 + j] * xv[j];
+        for (int j = 0; j < 2; ++j) acc -= L[i * 2 + j] * uv[j];
+        co[i] = acc;
+    }
+    for (int i = 0; i < 16; ++i) Fo[i] = F[i];
+    for (int i = 0; i < 8; ++i) Lo[i] = L[i];
+    g.ubar[k * 2] = a;
+    g.ubar[k * 2 + 1] = w;
+}
+
+// max |u_new - ubar| over the horizon into *out (ordered as the bit patterns
+// of non-negative doubles; *out starts at zero).
+template <typename OT>
+__global__ __launch_bounds__(kNlBlock) void k_nl_change(NlArgs g, unsigned long long* out) {
+    __shared__ double sh[kNlBlock];
+    const OT* u = (const OT*)g.u;
+    const int64_t n = g.T * 2;
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNlBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNlBlock)
+        mx = fmax(mx, fabs((double)u[i] - g.ubar[i]));
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = kNlBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // a NaN difference is reported as +inf
+        const double v = (sh[0] == sh[0]) ? sh[0] : __builtin_inf();
+        atomicMax(out, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// Zero `count` doubles (the change words and the round status words).
+__global__ void k_nl_zero(double* p, int count, int32_t* st, int nst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p && i < count) p[i] = 0.0;
+    if (st && i < nst) st[i] = 0;
+}
+
+// The first non-zero round status into *out.
+__global__ void k_nl_status(const int32_t* st, int n, int32_t* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t v = 0;
+    for (int i = 0; i < n && v == 0; ++i) v = st[i];
+    *out = v;
+}
+
+unsigned grid_for(int64_t count) { return (unsigned)((count + kNlBlock - 1) / kNlBlock); }
+
+}  // namespace
+
+hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipStream_t s) {
+    const int n = iterations > 0 ? iterations : 1;
+    k_nl_zero<<<(n + 255) / 256, 256, 0, s>>>(change, iterations, round_status, iterations);
+    return hipGetLastError();
+}
+
+hipError_t nl_linearise(const NlArgs& g, hipStream_t s) {
+    if (g.f32) k_nl_linearise_unicycle<float><<<grid_for(g.T), kNlBlock, 0, s>>>(g);
+    else k_nl_linearise_unicycle<double><<<grid_for(g.T), kNlBlock, 0, s>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s) {
+    if (!out) return hipSuccess;
+    const unsigned grid = grid_for(g.T * 2) < 1024u ? grid_for(g.T * 2) : 1024u;
+    if (g.f32) k_nl_change<float><<<grid, kNlBlock, 0, s>>>(g, (unsigned long long*)out);
+    else k_nl_change<double><<<grid, kNlBlock, 0, s>>>(g, (unsigned long long*)out);
+    return hipGetLastError();
+}
+
+hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s) {
+    if (!status) return hipSuccess;
+    k_nl_status<<<1, 64, 0, s>>>(round_status, iterations, status);
+    return hipGetLastError();
+}
+
+}  // namespace lqt

@@ -189,6 +189,7 @@ struct lqt_plan_s {
     int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
     lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
     bool has_side = false;
+    Arena nl;                // iterated linearisation: linearised model, nominal controls, round status
 };
 
 namespace {
@@ -942,6 +943,73 @@ lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats* out) {
     return LQT_OK;
 }
 
+lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t iterations, void* x, void* u,
+                          double* change, int32_t* status, void* stream) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_nl_iterate: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (!prob || !x || !u) return fail(plan, LQT_EINVAL, "lqt_nl_iterate: NULL problem or trajectory");
+    if (prob->model != LQT_NL_UNICYCLE) return fail(plan, LQT_EINVAL, "lqt_nl_iterate: unknown model %d",
+                                                    (int)prob->model);
+    if (iterations < 1) return fail(plan, LQT_EINVAL, "lqt_nl_iterate: iterations must be >= 1 (got %d)",
+                                    iterations);
+    if (prob->per_step & ~(uint32_t)(LQT_PS_H | LQT_PS_X | LQT_PS_U))
+        return fail(plan, LQT_EINVAL, "lqt_nl_iterate: only H, X and U may carry a time axis (per_step=0x%x)",
+                    prob->per_step);
+    if (!prob->dt) return fail(plan, LQT_EINVAL, "lqt_nl_iterate: dt is NULL");
+    const int n = 4, m = 2;
+    const int64_t T = prob->T;
+    // the instance of every round: the linearised model (workspace) and the cost
+    lqt_problem p{};
+    p.nx = n; p.nu = m; p.ny = prob->ny; p.nyT = prob->nyT; p.T = T;
+    p.per_step = prob->per_step | LQT_PS_F | LQT_PS_c | LQT_PS_L;
+    p.H = prob->H; p.X = prob->X; p.U = prob->U; p.r = prob->r;
+    p.HT = prob->HT; p.XT = prob->XT; p.rT = prob->rT; p.x0 = prob->x0;
+    lqt_outputs o{};
+    o.x = x;
+    o.u = u;
+    // validation with stand-in model pointers (replaced below)
+    p.F = p.L = p.c = prob->x0;
+    lqt_status st = validate(plan, p, o, 0);
+    if (st != LQT_OK) return st;
+    if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    const size_t model = align_up((size_t)T * (n * n + n * m + n + m) * sizeof(double));
+    st = ensure_ws(plan, plan->nl, model + align_up((size_t)iterations * sizeof(int32_t)));
+    if (st != LQT_OK) return st;
+    lqt::NlArgs g{};
+    g.dt = prob->dt;
+    g.T = T;
+    g.x = x;
+    g.u = u;
+    g.F = (double*)plan->nl.ws;
+    g.L = g.F + (size_t)T * n * n;
+    g.c = g.L + (size_t)T * n * m;
+    g.ubar = g.c + (size_t)T * n;
+    g.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
+    int32_t* round_status = (int32_t*)(plan->nl.ws + model);
+    p.F = g.F; p.L = g.L; p.c = g.c;
+    hipStream_t s = (hipStream_t)stream;
+    auto launched = [&](hipError_t e) -> lqt_status {
+        return e == hipSuccess ? LQT_OK : fail(plan, LQT_EHIP, "launch failed: %s", hipGetErrorString(e));
+    };
+    if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
+    for (int it = 0; it < iterations; ++it) {
+        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_linearise", s);
+        st = launched(lqt::nl_linearise(g, s));
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        if (st != LQT_OK) return st;
+        o.status = round_status + it;
+        if ((st = solve_all(plan, plan->main, &p, &o, 1, s, nullptr)) != LQT_OK) return st;
+        if (change) {
+            if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
+            st = launched(lqt::nl_change(g, change + it, s));
+            if (plan->prof.on) Profiler::end(&plan->prof, s);
+            if (st != LQT_OK) return st;
+        }
+    }
+    return launched(lqt::nl_finish(round_status, iterations, status, s));
+}
+
 lqt_status lqt_destroy(lqt_plan_t plan) {
     if (!plan) return LQT_OK;
     (void)hipSetDevice(plan->desc.device);
@@ -965,6 +1033,7 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
     }
     for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
     arena_release(plan->main);
+    arena_release(plan->nl);
     delete plan;
     return LQT_OK;
 }
