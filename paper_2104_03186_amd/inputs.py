@@ -233,7 +233,7 @@ def generalised_problem(n: int, m: int, T: int, seed: int, p: Optional[int] = No
 @dataclasses.dataclass
 class UnicycleProblem:
     """Nonlinear tracking with the unicycle model of the nonlinear experiment
-    (Section VI): state (p_x, p_y, theta, speed), control (acceleration, turn
+    (Section VI-E): state (p_x, p_y, theta, speed), control (acceleration, turn
     rate), x_{k+1} = f(x_k, u_k; dt_k); running cost
     1/2 (H x - r_k)^T X_k (H x - r_k) + 1/2 u^T U u, terminal
     1/2 (H_T x - r_T)^T X_T (H_T x - r_T).  X carries a time axis (weights
@@ -299,3 +299,56 @@ def unicycle_problem(T: int, seed: int = 0, ref_every: int = 5, dt: float = 0.1,
                            r=np.ascontiguousarray(r), HT=H.copy(), XT=lo * np.eye(3),
                            rT=np.array([pos[T, 0], pos[T, 1], heading[T]]), x0=x0,
                            xbar=np.ascontiguousarray(xbar), ubar=np.zeros((T, 2)))
+
+
+@dataclasses.dataclass
+class FiniteProblem:
+    """Finite state and control spaces (Section III-D): next [Dx][Du] or
+    [T][Dx][Du] (int32, -1 = not admissible), cost of the same shape
+    (float64), cost_T [Dx], initial state x0."""
+    nstates: int
+    ncontrols: int
+    T: int
+    next: np.ndarray
+    cost: np.ndarray
+    cost_T: np.ndarray
+    x0: int
+
+
+def routing_problem(T: int, nstates: int = 11, seed: int = 0) -> FiniteProblem:
+    """The aircraft-routing workload of the finite-state experiment (Section
+    VI-D; its cost grid is shown only in a figure): states are altitude
+    levels 0..Dx-1, controls up / straight / down (the two moves cost one
+    unit, straight nothing, no move leaves the grid), every grid point costs
+    0, 1 or 2 (seeded uniform), the terminal cost is the last column's grid
+    cost, the start is the middle level.  Integer-valued costs."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, 8, seed])))
+    D = nstates
+    grid = rng.integers(0, 3, size=(T + 1, D)).astype(np.float64)
+    nxt = np.empty((D, 3), dtype=np.int32)
+    for i in range(D):
+        nxt[i] = [i + 1 if i + 1 < D else -1, i, i - 1 if i >= 1 else -1]
+    move = np.array([1.0, 0.0, 1.0])
+    cost = grid[:T, :, None] + move[None, None, :]
+    return FiniteProblem(nstates=D, ncontrols=3, T=T, next=nxt, cost=np.ascontiguousarray(cost),
+                         cost_T=np.ascontiguousarray(grid[T]), x0=D // 2)
+
+
+def random_finite_problem(T: int, nstates: int, ncontrols: int, seed: int, per_step: int = 3,
+                          integer: bool = True, p_blocked: float = 0.2) -> FiniteProblem:
+    """Random tables: next states uniform (a fraction p_blocked not
+    admissible), costs uniform on 0..9 (integer-valued) or U[0, 10)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, 9, seed])))
+    D, Du = nstates, ncontrols
+    shape_n = (T, D, Du) if per_step & 1 else (D, Du)
+    shape_c = (T, D, Du) if per_step & 2 else (D, Du)
+    nxt = rng.integers(0, D, size=shape_n).astype(np.int32)
+    nxt[rng.random(size=shape_n) < p_blocked] = -1
+    if integer:
+        cost = rng.integers(0, 10, size=shape_c).astype(np.float64)
+        cost_T = rng.integers(0, 10, size=D).astype(np.float64)
+    else:
+        cost = rng.uniform(0.0, 10.0, size=shape_c)
+        cost_T = rng.uniform(0.0, 10.0, size=D)
+    return FiniteProblem(nstates=D, ncontrols=Du, T=T, next=np.ascontiguousarray(nxt),
+                         cost=np.ascontiguousarray(cost), cost_T=cost_T, x0=int(rng.integers(0, D)))
