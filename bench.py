@@ -286,8 +286,8 @@ def run_dense(args, api, inputs, torch, prec):
 
 
 def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
-    """Iterated linearisation (Section IV-E) on the unicycle of the nonlinear
-    experiment (Section VI): T = args.nl_T steps, args.nl_rounds rounds per
+    """Iterated linearisation (the nonlinear extension of Section IV-D) on the unicycle of the nonlinear
+    experiment (Section VI-E): T = args.nl_T steps, args.nl_rounds rounds per
     solve (the experiment: T = 1e5, 10 rounds), synthetic race track.  One
     timed solve = restore the nominal trajectory (device copy) + all rounds.
     The oracle's sequential iteration (the same rounds) is the parity
@@ -344,6 +344,100 @@ def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
             "value": round(T * rounds / (ms / 1e3), 1), "unit": "steps*rounds/s", "status": st,
             "rel_err": rel_err, "cpu_baseline": cpu,
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+
+
+def run_finite(args, api, inputs, torch, with_cpu=True):
+    """Finite state and control spaces (Section III-D), the routing workload
+    of the finite-state experiment (Section VI-D) at its state counts
+    D_x = 5, 11, 21 and T = args.fs_T.  Integer-valued costs: parity with the
+    oracle is exact.  Algorithmic bytes per step: the cost table row read
+    twice (product fold and final walk, 8 D_x D_u each), the closed-loop map
+    written once and read once (4 D_x each), V_k, u_k written (12 D_x), x_k
+    and the applied control written (8)."""
+    import oracle.finite as fin
+
+    T = args.fs_T
+    out = {}
+    for D in (5, 11, 21):
+        prob = inputs.routing_problem(T, nstates=D, seed=0)
+        plan = api.Plan(4, 4, prec="fp64", device=0)
+        dp = api.DeviceFSProblem(prob)
+        do = api.DeviceFSOutputs(D, T)
+        stream = torch.cuda.current_stream(0)
+        plan.fs_solve(dp, do, stream)
+        torch.cuda.synchronize()
+        st = int(do.status.item())
+        exact, cpu = None, None
+        if not args.no_parity or with_cpu:
+            t0 = time.perf_counter()
+            ref = fin.solve(prob)
+            secs = time.perf_counter() - t0
+            if not args.no_parity:
+                got = do.host()
+                exact = all(np.array_equal(got[f], ref[f]) for f in got)
+            if with_cpu:
+                cpu = {"value": round(T / secs, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+                       "sample": f"one full sequential solve (T={T}; {secs:.2f} s)"}
+        plan.profile(True)
+        plan.profile_read()
+        plan.fs_solve(dp, do, stream)
+        stages = plan.profile_read()
+        plan.profile(False)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.fs_steps):
+            plan.fs_solve(dp, do, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.fs_steps
+        plan.close()
+        Du = prob.ncontrols
+        bytes_step = 2 * 8 * D * Du + 8 * D + 12 * D + 8
+        out[f"D{D}"] = {"workload": f"finite-state routing, D_x={D}, D_u={Du}, T={T}", "ms_per_solve": round(ms, 4),
+                        "value": round(T / (ms / 1e3), 1), "unit": "steps/s", "status": st, "exact_parity": exact,
+                        "algorithmic_bytes_per_step": bytes_step,
+                        "hbm_frac": round(bytes_step * T / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "cpu_baseline": cpu,
+                        "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+    return out
+
+
+def run_blocks(args, api, inputs, torch):
+    """Block processing (Section V-C): every lane of the n <= 4 pipeline folds
+    a block of B consecutive elements sequentially before the parallel scan
+    over the blocks.  Time of the T = args.T tracking solve (FP64) for
+    B = 1 .. 64 (the library's default for this T is 16)."""
+    n, m, T = 4, 2, args.T
+    prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
+    plan = api.Plan(n, m, prec="fp64", device=0, max_steps=T)
+    dp = api.DeviceProblem(prob)
+    do = api.DeviceOutputs(n, m, T)
+    stream = torch.cuda.current_stream(0)
+    saved = os.environ.pop("LQT_CHUNK", None)
+    res = {}
+    try:
+        for B in (1, 2, 4, 8, 12, 16, 24, 32, 64):
+            os.environ["LQT_CHUNK"] = str(B)
+            for _ in range(2):
+                plan.solve([dp], [do], stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.block_steps):
+                plan.solve([dp], [do], stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[str(B)] = round(e0.elapsed_time(e1) / args.block_steps, 4)
+    finally:
+        os.environ.pop("LQT_CHUNK", None)
+        if saved is not None:
+            os.environ["LQT_CHUNK"] = saved
+        plan.close()
+    best = min(res, key=res.get)
+    return {"workload": f"block length sweep, tracking n=4 m=2 T={T} fp64", "ms_per_solve_by_block": res,
+            "best_block": int(best)}
 
 
 def run_copy(args, torch):
@@ -457,8 +551,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "nonlinear", "copy"),
-                    default="all")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "nonlinear", "finite",
+                                           "blocks", "copy"), default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
@@ -469,6 +563,9 @@ def main():
     ap.add_argument("--nl-T", type=int, default=100_000)
     ap.add_argument("--nl-rounds", type=int, default=10)
     ap.add_argument("--nl-steps", type=int, default=5)
+    ap.add_argument("--block-steps", type=int, default=20)
+    ap.add_argument("--fs-T", type=int, default=100_000)
+    ap.add_argument("--fs-steps", type=int, default=20)
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
@@ -501,6 +598,12 @@ def main():
     if args.workload == "nonlinear":
         print(json.dumps(run_nonlinear(args, api, inputs, torch, args.prec or "fp64",
                                        not args.no_cpu_baseline)), flush=True)
+        return
+    if args.workload == "blocks":
+        print(json.dumps(run_blocks(args, api, inputs, torch)), flush=True)
+        return
+    if args.workload == "finite":
+        print(json.dumps(run_finite(args, api, inputs, torch, not args.no_cpu_baseline)), flush=True)
         return
     if args.workload == "serving":
         print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed")), flush=True)
@@ -543,6 +646,8 @@ def main():
         out["single_fp64_generalised_cost"] = {k: gen[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                    "stages_avg_ms")}
         out["nonlinear_fp64"] = run_nonlinear(args, api, inputs, torch, "fp64", not args.no_cpu_baseline)
+        out["finite_state"] = run_finite(args, api, inputs, torch, not args.no_cpu_baseline)
+        out["block_sweep"] = run_blocks(args, api, inputs, torch)
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
         out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")

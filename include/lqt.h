@@ -224,7 +224,7 @@ typedef struct {
 
 lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats *out);
 
-/* Iterated linearisation for nonlinear dynamics (Section IV-E): starting
+/* Iterated linearisation for nonlinear dynamics (the nonlinear extension of Section IV-D): starting
  * from a nominal trajectory (xbar, ubar), each iteration linearises the
  * dynamics by the first-order Taylor expansion about the nominal,
  * x_{k+1} = F_k x_k + c_k + L_k u_k with F_k = df/dx, L_k = df/du at
@@ -233,7 +233,7 @@ lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats *out);
  * its optimal (x, u) as the next nominal.  Output and control maps are linear
  * (h(x) = H x, g(u) = u); the cost is that of lqt_problem. */
 typedef enum {
-    /* Unicycle of the nonlinear experiment (Section VI): x = (p_x, p_y,
+    /* Unicycle of the nonlinear experiment (Section VI-E): x = (p_x, p_y,
      * theta, speed), u = (acceleration, turn rate), f(x, u) = (p_x + speed
      * cos(theta) dt_k, p_y + speed sin(theta) dt_k, theta + turn rate dt_k,
      * speed + acceleration dt_k); nx = 4, nu = 2. */
@@ -264,6 +264,47 @@ typedef struct {
  * the checks of lqt_solve on the linearised instance. */
 lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem *prob, int32_t iterations, void *x, void *u,
                           double *change, int32_t *status, void *stream);
+
+/* Finite state and control spaces (Section III-D): x_k in {0..D_x-1},
+ * u_k in {0..D_u-1}, x_{k+1} = f_k(x_k, u_k), stage cost l_k(x_k, u_k),
+ * terminal cost l_T(x_T).  The value functions V_k(x) = min_u { l_k(x, u) +
+ * V_{k+1}(f_k(x, u)) } come from a reverse scan whose elements are the
+ * one-step conditional value functions V_{k->k+1}(x, y) = min { l_k(x, u) :
+ * f_k(x, u) = y } (D_x x D_x, +inf where y is unreachable) combined by the
+ * min-plus product (the combination rule of Section III-B); the control law
+ * u_k(x) is the minimising control (the smallest index among equal minima),
+ * and the trajectory from x_0 follows by composing the closed-loop maps
+ * x -> f_k(x, u_k(x)) (Method 1 of Section III-C).  Costs are doubles;
+ * with integer-valued costs every sum is exact and the results do not
+ * depend on the association order of the scan. */
+enum { LQT_FS_NEXT = 1, LQT_FS_COST = 2 };  /* per_step bits of lqt_fs_problem */
+
+typedef struct {
+    int32_t nstates, ncontrols;  /* D_x in 1..32, D_u in 1..32                           */
+    int64_t T;                   /* control steps, T >= 1                                */
+    uint32_t per_step;           /* LQT_FS_* bits: table with a leading time axis        */
+    const int32_t *next;         /* [D_x][D_u] or [T][D_x][D_u]: f_k(x, u); -1 = control not admissible */
+    const double *cost;          /* [D_x][D_u] or [T][D_x][D_u]: l_k(x, u)               */
+    const double *cost_T;        /* [D_x] terminal cost                                  */
+    int32_t x0;                  /* initial state                                        */
+} lqt_fs_problem;
+
+typedef struct {
+    double *V;        /* [T+1][D_x] value functions (+inf: no admissible continuation), or NULL */
+    int32_t *u;       /* [T][D_x] control law (-1 where no control is admissible), or NULL      */
+    int32_t *x;       /* [T+1] optimal trajectory from x0, or NULL                               */
+    int32_t *ux;      /* [T] the controls applied along it, or NULL                              */
+    int32_t *status;  /* optional device int32: LQT_OK, or LQT_ENONFINITE when no admissible path leaves x0 */
+} lqt_fs_outputs;
+
+/* Solve one finite-state problem on `stream` (stream-ordered, asynchronous).
+ * All pointers are device pointers; next, cost, cost_T and the outputs
+ * are caller-owned.  LQT_EINVAL (nothing enqueued): D_x or D_u outside
+ * 1..32, T < 1, x0 outside 0..D_x-1, NULL tables, unknown per_step bits.
+ * Next-state entries outside -1..D_x-1 are treated as not admissible.
+ * Workspace: about (D_x^2 + 2 D_x) T / B doubles with B >= T / 256, plus
+ * D_x T int32 (the closed-loop maps of every step). */
+lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem *prob, const lqt_fs_outputs *out, void *stream);
 
 /* Wait for all work of the plan, then release it and its workspace. */
 lqt_status lqt_destroy(lqt_plan_t plan);

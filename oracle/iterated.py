@@ -1,5 +1,5 @@
-"""Iterated linearisation for nonlinear control (Section IV-E) with the
-unicycle model of the nonlinear experiment (Section VI).
+"""Iterated linearisation for nonlinear control (the nonlinear extension of Section IV-D) with the
+unicycle model of the nonlinear experiment (Section VI-E).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU leg, never by the product package; it shares no code with
@@ -25,7 +25,7 @@ PS_F, PS_c, PS_L, PS_X = 1, 2, 4, 16
 
 
 def unicycle_f(x: np.ndarray, u: np.ndarray, dt: float) -> np.ndarray:
-    """Discretised unicycle (Section VI): position advanced along the heading
+    """Discretised unicycle (Section VI-E): position advanced along the heading
     by speed * dt, heading by the turn rate, speed by the acceleration."""
     px, py, th, s = x
     a, w = u

@@ -21,7 +21,8 @@ TRAJ_MAPS, TRAJ_PREFIX = 0, 1
 PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
-            "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate")
+            "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate",
+            "lqt_fs_solve")
 
 _vp = ctypes.c_void_p
 
@@ -40,6 +41,18 @@ class NLProblem(ctypes.Structure):
 
 
 NL_UNICYCLE = 0
+
+
+class FSProblem(ctypes.Structure):
+    _fields_ = [("nstates", ctypes.c_int32), ("ncontrols", ctypes.c_int32), ("T", ctypes.c_int64),
+                ("per_step", ctypes.c_uint32), ("next", _vp), ("cost", _vp), ("cost_T", _vp), ("x0", ctypes.c_int32)]
+
+
+class FSOutputs(ctypes.Structure):
+    _fields_ = [("V", _vp), ("u", _vp), ("x", _vp), ("ux", _vp), ("status", _vp)]
+
+
+FS_NEXT, FS_COST = 1, 2
 
 
 class Outputs(ctypes.Structure):
@@ -104,6 +117,8 @@ def load() -> ctypes.CDLL:
     lib.lqt_profile_read.restype = ctypes.c_int32
     lib.lqt_nl_iterate.argtypes = [_vp, ctypes.POINTER(NLProblem), ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
     lib.lqt_nl_iterate.restype = ctypes.c_int
+    lib.lqt_fs_solve.argtypes = [_vp, ctypes.POINTER(FSProblem), ctypes.POINTER(FSOutputs), _vp]
+    lib.lqt_fs_solve.restype = ctypes.c_int
     lib.lqt_last_error.argtypes = [_vp]
     lib.lqt_last_error.restype = ctypes.c_char_p
     _lib = lib

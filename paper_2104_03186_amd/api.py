@@ -45,8 +45,8 @@ class DeviceProblem:
 
 class DeviceNLProblem:
     """A nonlinear tracking instance for the iterated linearisation (Section
-    IV-E) resident in device memory; ``prob`` has the attributes of
-    inputs.UnicycleProblem (model: the unicycle of Section VI)."""
+    IV-D, nonlinear extension) resident in device memory; ``prob`` has the attributes of
+    inputs.UnicycleProblem (model: the unicycle of Section VI-E)."""
 
     FIELDS = ("dt", "H", "X", "U", "r", "HT", "XT", "rT", "x0")
 
@@ -63,6 +63,48 @@ class DeviceNLProblem:
         for f in self.FIELDS:
             setattr(s, f, _ptr(self.t[f]))
         return s
+
+
+class DeviceFSProblem:
+    """A finite state and control problem (Section III-D) resident in device
+    memory; ``prob`` has the attributes of inputs.FiniteProblem."""
+
+    def __init__(self, prob, device="cuda:0"):
+        self.D, self.Du, self.T, self.x0 = int(prob.nstates), int(prob.ncontrols), int(prob.T), int(prob.x0)
+        nxt, cost = np.asarray(prob.next), np.asarray(prob.cost)
+        self.per_step = (_lib.FS_NEXT if nxt.ndim == 3 else 0) | (_lib.FS_COST if cost.ndim == 3 else 0)
+        self.t = {"next": torch.from_numpy(np.ascontiguousarray(nxt, dtype=np.int32)).to(device),
+                  "cost": torch.from_numpy(np.ascontiguousarray(cost, dtype=np.float64)).to(device),
+                  "cost_T": torch.from_numpy(np.ascontiguousarray(prob.cost_T, dtype=np.float64)).to(device)}
+
+    def struct(self) -> _lib.FSProblem:
+        s = _lib.FSProblem()
+        s.nstates, s.ncontrols, s.T, s.per_step, s.x0 = self.D, self.Du, self.T, self.per_step, self.x0
+        for f, t in self.t.items():
+            setattr(s, f, _ptr(t))
+        return s
+
+
+class DeviceFSOutputs:
+    """Outputs of a finite-state solve: V [T+1][D] (float64), u [T][D], x
+    [T+1], ux [T] (int32); ``want`` selects them (others NULL)."""
+
+    def __init__(self, D: int, T: int, device="cuda:0", want: Iterable[str] = ("V", "u", "x", "ux")):
+        want = set(want)
+        spec = {"V": ((T + 1, D), torch.float64), "u": ((T, D), torch.int32), "x": ((T + 1,), torch.int32),
+                "ux": ((T,), torch.int32)}
+        self.t = {k: (torch.empty(sh, dtype=dt, device=device) if k in want else None) for k, (sh, dt) in spec.items()}
+        self.status = torch.full((1,), -1, dtype=torch.int32, device=device)
+
+    def struct(self) -> _lib.FSOutputs:
+        s = _lib.FSOutputs()
+        for k, t in self.t.items():
+            setattr(s, k, _ptr(t))
+        s.status = _ptr(self.status)
+        return s
+
+    def host(self) -> Dict[str, np.ndarray]:
+        return {k: v.cpu().numpy() for k, v in self.t.items() if v is not None}
 
 
 class DeviceOutputs:
@@ -169,6 +211,14 @@ class Plan:
         _lib.check(_lib.load().lqt_nl_iterate(self._h, ctypes.byref(ps), int(iterations), _ptr(x), _ptr(u),
                                               _ptr(change), _ptr(status), ctypes.c_void_p(stream.cuda_stream)),
                    self._h)
+
+    def fs_solve(self, prob: "DeviceFSProblem", out: "DeviceFSOutputs", stream=None) -> None:
+        """Finite state and control problem (lqt_fs_solve).  Asynchronous."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        ps, os_ = prob.struct(), out.struct()
+        _lib.check(_lib.load().lqt_fs_solve(self._h, ctypes.byref(ps), ctypes.byref(os_),
+                                            ctypes.c_void_p(stream.cuda_stream)), self._h)
 
     def submit(self, prob: DeviceProblem, out: DeviceOutputs) -> int:
         self._check_dtype(out)

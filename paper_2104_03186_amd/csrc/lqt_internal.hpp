@@ -114,7 +114,7 @@ void gen_layout(GenArgs& g, double* ws);
 hipError_t gen_transform(const GenArgs& g, hipStream_t s);
 hipError_t gen_post(const GenArgs& g, hipStream_t s);
 
-// Iterated linearisation (Section IV-E), unicycle model: one round's
+// Iterated linearisation (the nonlinear extension of Section IV-D), unicycle model: one round's
 // expansion of the dynamics about the nominal (x, u: the plan's output type)
 // into per-step F, L, c, plus a double copy of the nominal controls.
 struct NlArgs {
@@ -128,5 +128,28 @@ hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipSt
 hipError_t nl_linearise(const NlArgs& g, hipStream_t s);
 hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s);
 hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s);
+
+// Finite state and control spaces (Section III-D).  The horizon is cut into
+// NC <= kFsMaxNC chunks of B steps, the chunks into groups of kFsGroup.
+constexpr int kFsMaxNC = 256;
+constexpr int kFsGroup = 16;
+struct FsArgs {
+    const int32_t* next;   // [D][Du] or [T][D][Du]
+    const double* cost;    // [D][Du] or [T][D][Du]
+    const double* cost_T;  // [D]
+    int64_t T;
+    int32_t D, Du;
+    uint32_t per_step;     // bit 0: next per step; bit 1: cost per step
+    int32_t x0;
+    int32_t B, NC, NG;
+    // outputs (V, x, ux, status may be null; ulaw is the caller's u or workspace)
+    double* V;
+    int32_t *ulaw, *x, *ux, *status;
+    // workspace
+    double *P, *Q, *gval, *cval;  // [NC][D][D], [NG][D][D], [NG + 1][D], [NC + 1][D]
+    int32_t *nxt, *phi, *xs;      // [T][D], [NC][D], [NC + 1]
+};
+void fs_shape(int64_t T, int32_t& B, int32_t& NC, int32_t& NG);
+hipError_t fs_solve(const FsArgs& a, hipStream_t s, const StageHook* h);
 
 }  // namespace lqt

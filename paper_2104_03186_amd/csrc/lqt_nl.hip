@@ -1,7 +1,7 @@
-// Iterated linearisation for nonlinear dynamics (Section IV-E): the device
+// Iterated linearisation for nonlinear dynamics (the nonlinear extension of Section IV-D): the device
 // side of one round -- the first-order Taylor expansion of the dynamics about
 // the nominal trajectory, and the round's convergence measure.  Model: the
-// unicycle of the nonlinear experiment (Section VI).
+// unicycle of the nonlinear experiment (Section VI-E).
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"

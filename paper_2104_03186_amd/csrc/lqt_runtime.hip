@@ -190,6 +190,7 @@ struct lqt_plan_s {
     lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
     bool has_side = false;
     Arena nl;                // iterated linearisation: linearised model, nominal controls, round status
+    Arena fs;                // finite-state solves: chunk and group products, values, closed-loop maps
 };
 
 namespace {
@@ -1010,6 +1011,55 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
     return launched(lqt::nl_finish(round_status, iterations, status, s));
 }
 
+lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem* prob, const lqt_fs_outputs* out, void* stream) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_fs_solve: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (!prob || !out) return fail(plan, LQT_EINVAL, "lqt_fs_solve: NULL problem or outputs");
+    const int D = prob->nstates, Du = prob->ncontrols;
+    if (D < 1 || D > 32 || Du < 1 || Du > 32)
+        return fail(plan, LQT_EINVAL, "lqt_fs_solve: states %d and controls %d must be in 1..32", D, Du);
+    if (prob->T < 1) return fail(plan, LQT_EINVAL, "lqt_fs_solve: T must be >= 1 (got %lld)", (long long)prob->T);
+    if (prob->x0 < 0 || prob->x0 >= D) return fail(plan, LQT_EINVAL, "lqt_fs_solve: x0=%d outside 0..%d", prob->x0,
+                                                   D - 1);
+    if (prob->per_step & ~(uint32_t)(LQT_FS_NEXT | LQT_FS_COST))
+        return fail(plan, LQT_EINVAL, "lqt_fs_solve: unknown per_step bits 0x%x", prob->per_step);
+    if (!prob->next || !prob->cost || !prob->cost_T)
+        return fail(plan, LQT_EINVAL, "lqt_fs_solve: a table pointer is NULL");
+    if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    lqt::FsArgs a{};
+    a.next = prob->next; a.cost = prob->cost; a.cost_T = prob->cost_T;
+    a.T = prob->T; a.D = D; a.Du = Du; a.per_step = prob->per_step; a.x0 = prob->x0;
+    lqt::fs_shape(a.T, a.B, a.NC, a.NG);
+    const size_t DD = (size_t)D * D;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t oP = take((size_t)a.NC * DD * sizeof(double));
+    const size_t oQ = take((size_t)a.NG * DD * sizeof(double));
+    const size_t oG = take((size_t)(a.NG + 1) * D * sizeof(double));
+    const size_t oC = take((size_t)(a.NC + 1) * D * sizeof(double));
+    const size_t oN = take((size_t)a.T * D * sizeof(int32_t));
+    const size_t oF = take((size_t)a.NC * D * sizeof(int32_t));
+    const size_t oX = take((size_t)(a.NC + 1) * sizeof(int32_t));
+    const size_t oU = take(out->u ? 0 : (size_t)a.T * D * sizeof(int32_t));
+    lqt_status st = ensure_ws(plan, plan->fs, off);
+    if (st != LQT_OK) return st;
+    char* w = plan->fs.ws;
+    a.P = (double*)(w + oP); a.Q = (double*)(w + oQ); a.gval = (double*)(w + oG); a.cval = (double*)(w + oC);
+    a.nxt = (int32_t*)(w + oN); a.phi = (int32_t*)(w + oF); a.xs = (int32_t*)(w + oX);
+    a.V = out->V;
+    a.ulaw = out->u ? out->u : (int32_t*)(w + oU);
+    a.x = out->x; a.ux = out->ux; a.status = out->status;
+    lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
+    hipError_t e = lqt::fs_solve(a, (hipStream_t)stream, plan->prof.on ? &hook : nullptr);
+    if (e != hipSuccess) return fail(plan, LQT_EHIP, "finite-state launch failed: %s", hipGetErrorString(e));
+    return LQT_OK;
+}
+
 lqt_status lqt_destroy(lqt_plan_t plan) {
     if (!plan) return LQT_OK;
     (void)hipSetDevice(plan->desc.device);
@@ -1034,6 +1084,7 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
     for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
     arena_release(plan->main);
     arena_release(plan->nl);
+    arena_release(plan->fs);
     delete plan;
     return LQT_OK;
 }

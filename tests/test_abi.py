@@ -58,6 +58,8 @@ STRUCTS = {
     "lqt_outputs": ("Outputs", ["S", "v", "K", "d", "x", "u", "status"]),
     "lqt_nl_problem": ("NLProblem", ["model", "ny", "nyT", "T", "per_step", "dt", "H", "X", "U", "r", "HT", "XT",
                                      "rT", "x0"]),
+    "lqt_fs_problem": ("FSProblem", ["nstates", "ncontrols", "T", "per_step", "next", "cost", "cost_T", "x0"]),
+    "lqt_fs_outputs": ("FSOutputs", ["V", "u", "x", "ux", "status"]),
     "lqt_plan_desc": ("PlanDesc", ["device", "max_nx", "max_nu", "prec", "hbm_budget_bytes", "max_steps",
                                    "max_inflight", "trajectory"]),
     "lqt_serve_stats": ("ServeStats", ["submitted", "completed", "batches", "queued", "running_batches",

@@ -1,5 +1,6 @@
-"""GPU parity of the iterated linearisation for nonlinear dynamics (Section
-IV-E) on the unicycle model of the nonlinear experiment (Section VI):
+"""GPU parity of the iterated linearisation for nonlinear dynamics (the
+nonlinear extension of Section IV-D) on the unicycle model of the nonlinear
+experiment (Section VI-E):
 lqt_nl_iterate against the oracle's linearise-and-solve iteration (pinned
 in tests/test_nonlinear_pins.py) with the same number of rounds, on the
 lane pipeline (both trajectory methods) and the wavefront engine, FP64 and

@@ -1,5 +1,5 @@
-"""Pins of the oracle's iterated linearisation (Section IV-E) with the unicycle
-model of the nonlinear experiment (Section VI).  CPU only.
+"""Pins of the oracle's iterated linearisation (the nonlinear extension of Section IV-D) with the unicycle
+model of the nonlinear experiment (Section VI-E).  CPU only.
 
 * the hand-written Jacobians against central finite differences of the
   model;
