@@ -131,8 +131,8 @@ hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* statu
 
 // Finite state and control spaces (Section III-D).  The horizon is cut into
 // NC <= kFsMaxNC chunks of B steps, the chunks into groups of kFsGroup.
-constexpr int kFsMaxNC = 256;
-constexpr int kFsGroup = 16;
+constexpr int kFsMaxNC = 2048;
+constexpr int kFsGroup = 32;
 struct FsArgs {
     const int32_t* next;   // [D][Du] or [T][D][Du]
     const double* cost;    // [D][Du] or [T][D][Du]
@@ -148,6 +148,7 @@ struct FsArgs {
     // workspace
     double *P, *Q, *gval, *cval;  // [NC][D][D], [NG][D][D], [NG + 1][D], [NC + 1][D]
     int32_t *nxt, *phi, *xs;      // [T][D], [NC][D], [NC + 1]
+    int32_t *gphi, *gxs;          // [NG][D] group maps, [NG + 1] states at group starts
 };
 void fs_shape(int64_t T, int32_t& B, int32_t& NC, int32_t& NG);
 hipError_t fs_solve(const FsArgs& a, hipStream_t s, const StageHook* h);

@@ -1046,11 +1046,14 @@ lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem* prob, const lqt_f
     const size_t oF = take((size_t)a.NC * D * sizeof(int32_t));
     const size_t oX = take((size_t)(a.NC + 1) * sizeof(int32_t));
     const size_t oU = take(out->u ? 0 : (size_t)a.T * D * sizeof(int32_t));
+    const size_t oGF = take((size_t)a.NG * D * sizeof(int32_t));
+    const size_t oGX = take((size_t)(a.NG + 1) * sizeof(int32_t));
     lqt_status st = ensure_ws(plan, plan->fs, off);
     if (st != LQT_OK) return st;
     char* w = plan->fs.ws;
     a.P = (double*)(w + oP); a.Q = (double*)(w + oQ); a.gval = (double*)(w + oG); a.cval = (double*)(w + oC);
     a.nxt = (int32_t*)(w + oN); a.phi = (int32_t*)(w + oF); a.xs = (int32_t*)(w + oX);
+    a.gphi = (int32_t*)(w + oGF); a.gxs = (int32_t*)(w + oGX);
     a.V = out->V;
     a.ulaw = out->u ? out->u : (int32_t*)(w + oU);
     a.x = out->x; a.ux = out->ux; a.status = out->status;
