@@ -38,7 +38,12 @@
  * error of a plan.
  *
  * Thread safety: the calls on one plan are serialised by a lock inside the
- * plan, so a plan may be shared by host threads.
+ * plan, so a plan may be shared by host threads.  The device workspace of a
+ * plan is shared by the work it enqueues (lqt_solve, lqt_nl_iterate and
+ * lqt_fs_solve each reuse their own region on every call): work of one plan
+ * enqueued on different streams must be ordered by the caller, or each
+ * stream given its own plan.  The serving interface (lqt_submit) manages
+ * its own streams and memory.
  */
 #ifndef LQT_H
 #define LQT_H
