@@ -40,6 +40,8 @@ struct SmallArgs {
     int32_t traj;      // forward pass: 0 = scan of the closed-loop maps, 1 = forward prefixes
     double* m2_el;     // [NC] in-wave prefixes of the chunk elements (traj 1)
     double* m2_val;    // [NG] (C, b) of the forward prefix at wavefront-unit starts (traj 1)
+    double* m2_mid;    // [NG] in-block prefixes of the unit totals (traj 1, NG > kSmallTopBlock)
+    double* m2_blk;    // [NB] (C, b) at block starts (traj 1, NG > kSmallTopBlock)
 };
 
 // Optional per-kernel timing hook: begin/end are called on the host around

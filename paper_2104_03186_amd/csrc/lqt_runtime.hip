@@ -222,7 +222,8 @@ int chunk_length(int64_t T) {
 }
 
 struct Layout {
-    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, m2_el, m2_val, S, v, total;
+    size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, m2_el, m2_val, m2_mid, m2_blk, S, v,
+        total;
     int64_t NC;
     int B, NG, NB;
 };
@@ -258,6 +259,8 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d, bool m2 = fals
     L.d = take(need_d ? (size_t)p.T * m : 0);
     L.m2_el = take(m2 ? (size_t)L.NC * small_elem_doubles(n) : 0);
     L.m2_val = take(m2 ? (size_t)L.NG * small_val_doubles(n) : 0);
+    L.m2_mid = take(m2 && blocks ? (size_t)L.NG * small_elem_doubles(n) : 0);
+    L.m2_blk = take(m2 && blocks ? (size_t)L.NB * small_val_doubles(n) : 0);
     L.S = take(m2 && need_S ? (size_t)(p.T + 1) * n * n : 0);
     L.v = take(m2 && need_v ? (size_t)(p.T + 1) * n : 0);
     L.total = off;
@@ -426,6 +429,8 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.traj = m2 ? 1 : 0;
     a.m2_el = (double*)(base + L.m2_el);
     a.m2_val = (double*)(base + L.m2_val);
+    a.m2_mid = (double*)(base + L.m2_mid);
+    a.m2_blk = (double*)(base + L.m2_blk);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr, plan->has_side ? &plan->side : nullptr);
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));

@@ -1198,24 +1198,27 @@ __global__ __launch_bounds__(kBlock) void k_m2_reduce(SmallArgs a) {
     if (active) store_elem<N>(a.m2_el + c * Elem<N>::size, P);
 }
 
-// One workgroup: (C, b) of V_{0->k} at the first step of every wavefront unit
-// g (m2_val[g]), from the unit totals (the in-wave prefix of each unit's last
-// lane) and x_0.
+// One workgroup: (C, b) of V_{0->k} at the start of every one of `cnt`
+// consecutive segments (out[g]), from the segment totals and x_0.  The total
+// of segment g is the prefix element el[last], last = min((g + 1) span, n_el)
+// - 1: wavefront units over the in-wave prefixes (span 64), or blocks of
+// kBlock units over the in-block prefixes of the unit totals.
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_m2_top(SmallArgs a) {
+__global__ __launch_bounds__(kBlock) void k_m2_top(SmallArgs a, const double* el, int span, int64_t n_el, int cnt,
+                                                   double* out) {
     using S = Sym<N>;
     constexpr int VS = S::size + N;
     __shared__ double sh[kBlock / kWave][Elem<N>::size];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
-    const int NG = a.NG;
+    const int NG = cnt;
     const int q = (NG + kBlock - 1) / kBlock;
     const int lo = tid * q < NG ? tid * q : NG;
     const int hi = lo + q < NG ? lo + q : NG;
     auto unit_total = [&](int g, Elem<N>& t) {
-        const int64_t last = ((int64_t)(g + 1) * kWave < a.NC ? (int64_t)(g + 1) * kWave : a.NC) - 1;
-        load_elem<N>(a.m2_el + last * Elem<N>::size, t);
+        const int64_t last = ((int64_t)(g + 1) * span < n_el ? (int64_t)(g + 1) * span : n_el) - 1;
+        load_elem<N>(el + last * Elem<N>::size, t);
     };
     Elem<N> agg, t;
     set_identity<N>(agg);
@@ -1246,12 +1249,73 @@ __global__ __launch_bounds__(kBlock) void k_m2_top(SmallArgs a) {
     LQT_UNROLL for (int i = 0; i < S::size; ++i) Cs[i] = 0.0;
     fanchor<N>(prev, b, Cs);
     for (int g = lo; g < hi; ++g) {
-        double* o = a.m2_val + (int64_t)g * VS;
+        double* o = out + (int64_t)g * VS;
         LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = Cs[i];
         LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = b[i];
         unit_total(g, t);
         fanchor<N>(t, b, Cs);
     }
+}
+
+// Long instances (more than kBlock wavefront units): k_m2_mid forms the
+// inclusive prefixes of the unit totals within each block of kBlock units
+// (one workgroup per block), k_m2_top the value at every block start, and
+// k_m2_down the value at every unit start: the block's start value advanced
+// by the in-block prefix of the units before it.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_m2_mid(SmallArgs a) {
+    __shared__ double sh[kBlock / kWave][Elem<N>::size];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g = g0 + tid;
+    const int nb = (int)(a.NG - g0 < kBlock ? a.NG - g0 : kBlock);
+    Elem<N> agg, t;
+    if (tid < nb) {
+        const int64_t last = ((g + 1) * kWave < a.NC ? (g + 1) * kWave : a.NC) - 1;
+        load_elem<N>(a.m2_el + last * Elem<N>::size, agg);
+    } else {
+        set_identity<N>(agg);
+    }
+    for (int d = 1; d < kWave; d <<= 1) {
+        Elem<N> Q = shfl_up_elem<N>(agg, d);
+        if (lane >= d) combine<N>(Q, agg);  // agg <- Q (x) agg
+    }
+    if (lane == kWave - 1) store_elem<N>(sh[wv], agg);
+    __syncthreads();
+    if (wv > 0) {
+        Elem<N> R;
+        load_elem<N>(sh[0], R);
+        for (int w = 1; w < wv; ++w) {
+            load_elem<N>(sh[w], t);
+            combine<N>(R, t);  // t <- R (x) t
+            R = t;
+        }
+        combine<N>(R, agg);
+    }
+    if (tid < nb) store_elem<N>(a.m2_mid + g * Elem<N>::size, agg);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_m2_down(SmallArgs a) {
+    using S = Sym<N>;
+    constexpr int VS = S::size + N;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.NG) return;
+    const int64_t b = g / kBlock;
+    double bb[N], Cs[S::size];
+    const double* bv = a.m2_blk + b * VS;
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) Cs[i] = bv[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) bb[i] = bv[S::size + i];
+    if (g > b * kBlock) {
+        Elem<N> e;
+        load_elem<N>(a.m2_mid + (g - 1) * Elem<N>::size, e);
+        fanchor<N>(e, bb, Cs);
+    }
+    double* o = a.m2_val + g * VS;
+    LQT_UNROLL for (int i = 0; i < S::size; ++i) o[i] = Cs[i];
+    LQT_UNROLL for (int i = 0; i < N; ++i) o[S::size + i] = bb[i];
 }
 
 // Lane c: (b, C) at its chunk's first step (its unit's value advanced by the
@@ -1385,8 +1449,21 @@ static void run_mode(const SmallArgs& a, hipStream_t s, const StageHook* h, cons
             Stage st(h, "m2_reduce", s2);
             k_m2_reduce<N, M, MODE><<<grid, kBlock, 0, s2>>>(a);
         }
-        Stage st(h, "m2_top", s2);
-        k_m2_top<N><<<1, kBlock, 0, s2>>>(a);
+        if (a.NG > kBlock) {
+            {
+                Stage st(h, "m2_mid", s2);
+                k_m2_mid<N><<<(unsigned)a.NB, kBlock, 0, s2>>>(a);
+            }
+            {
+                Stage st(h, "m2_top", s2);
+                k_m2_top<N><<<1, kBlock, 0, s2>>>(a, a.m2_mid, kBlock, a.NG, a.NB, a.m2_blk);
+            }
+            Stage st(h, "m2_down", s2);
+            k_m2_down<N><<<(unsigned)a.NB, kBlock, 0, s2>>>(a);
+        } else {
+            Stage st(h, "m2_top", s2);
+            k_m2_top<N><<<1, kBlock, 0, s2>>>(a, a.m2_el, kWave, a.NC, a.NG, a.m2_val);
+        }
     }
     {
         Stage st(h, "bwd_reduce", s);
