@@ -10,9 +10,9 @@
 //                (D x D, folded right to left; E_k never formed:
 //                (E_k (x) P)(x, y) = min_u l_k(x, u) + P(f_k(x, u), y));
 //   k_fs_group   one workgroup per group: Q_g = P_{c0} (x) ... (x) P_{c1-1};
-//   k_fs_top     one wavefront: V at every group start from V_T (min-plus
+//   k_fs_top     one workgroup: V at every group start from V_T (min-plus
 //                matrix-vector products, lanes = states);
-//   k_fs_gdown   one wavefront per group: V at every chunk start;
+//   k_fs_gdown   one workgroup per group: V at every chunk start;
 //   k_fs_final   one wavefront per chunk: V_k, u_k and the closed-loop next
 //                state of every step (lanes = states, V_{k+1} shuffled across
 //                the lanes), and the chunk's composed map phi_c;
@@ -36,6 +36,29 @@ constexpr int kWaveFs = 64;
 constexpr int kFsMaxD = 32;
 constexpr int kFsStage = 64;          // steps staged per round of the forward walk
 constexpr int kSlabBytes = 32 * 1024;  // LDS for the step tables of a slab of steps
+constexpr int kGroupLds = 40 * 1024;   // LDS for a batch of chunk products in the group fold
+
+// Copy n elements from global memory into LDS (thread tid of nt), eight
+// loads in flight per thread before their stores: a load followed at once by
+// its LDS store would wait for that load, one global-memory latency per
+// element.  op is applied to every value on the way.
+template <typename T, typename Op>
+__device__ __forceinline__ void stage_copy(T* dst, const T* src, int64_t n, int tid, int nt, Op op) {
+    int64_t e = tid;
+    for (; e + 7 * (int64_t)nt < n; e += 8 * (int64_t)nt) {
+        T r[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = src[e + q * nt];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[e + q * nt] = op(r[q]);
+    }
+    for (; e < n; e += nt) dst[e] = op(src[e]);
+}
+
+struct Same {
+    template <typename T>
+    __device__ T operator()(T v) const { return v; }
+};
 
 // Steps per slab of staged tables (at least one).
 __device__ __forceinline__ int fs_slab_steps(const FsArgs& a) {
@@ -55,11 +78,9 @@ __device__ __forceinline__ void fs_stage(const FsArgs& a, int64_t ks, int64_t ke
     const int64_t nc = (a.per_step & 2) ? n_steps * row : row;
     const int32_t* gn = a.next + ((a.per_step & 1) ? ks * row : 0);
     const double* gc = a.cost + ((a.per_step & 2) ? ks * row : 0);
-    for (int64_t e = tid; e < nn; e += nthreads) {
-        const int v = gn[e];
-        nx[e] = (v >= 0 && v < a.D) ? v : -1;
-    }
-    for (int64_t e = tid; e < nc; e += nthreads) cs[e] = gc[e];
+    const int D = a.D;
+    stage_copy(nx, gn, nn, tid, nthreads, [D](int32_t v) { return (v >= 0 && v < D) ? v : -1; });
+    stage_copy(cs, gc, nc, tid, nthreads, Same{});
 }
 
 // Offsets of step j of a slab in the staged tables.
@@ -76,6 +97,17 @@ __global__ __launch_bounds__(kFsBlock) void k_fs_reduce(FsArgs a) {
     const int64_t k0 = c * a.B;
     const int64_t k1 = (k0 + a.B < a.T) ? k0 + a.B : a.T;
     const int S = fs_slab_steps(a);
+    // the entries of this thread (e = t + q kFsBlock): row offset i Du in the
+    // step tables and column j, fixed for the whole fold
+    constexpr int kEntries = kFsMaxD * kFsMaxD / kFsBlock;
+    int erow[kEntries], ecol[kEntries];
+    const int ne = t < DD ? (DD - t + kFsBlock - 1) / kFsBlock : 0;
+#pragma unroll
+    for (int q = 0; q < kEntries; ++q) {
+        const int e = t + q * kFsBlock;
+        erow[q] = (e / D) * Du;
+        ecol[q] = e % D;
+    }
     for (int e = t; e < DD; e += kFsBlock) P[0][e] = (e / D == e % D) ? 0.0 : __builtin_inf();
     int cur = 0;
     for (int64_t ke = k1; ke > k0; ke -= S) {
@@ -85,14 +117,16 @@ __global__ __launch_bounds__(kFsBlock) void k_fs_reduce(FsArgs a) {
         __syncthreads();
         for (int64_t k = ke - 1; k >= ks; --k) {
             const int jn = fs_nrow(a, (int)(k - ks)), jc = fs_crow(a, (int)(k - ks));
-            for (int e = t; e < DD; e += kFsBlock) {
-                const int i = e / D, j = e - (e / D) * D;
-                double acc = __builtin_inf();
-                for (int u = 0; u < Du; ++u) {
-                    const int to = nx[jn + i * Du + u];
-                    if (to >= 0) acc = fmin(acc, cs[jc + i * Du + u] + P[cur][to * D + j]);
+#pragma unroll
+            for (int q = 0; q < kEntries; ++q) {
+                if (q < ne) {
+                    double acc = __builtin_inf();
+                    for (int u = 0; u < Du; ++u) {
+                        const int to = nx[jn + erow[q] + u];
+                        if (to >= 0) acc = fmin(acc, cs[jc + erow[q] + u] + P[cur][to * D + ecol[q]]);
+                    }
+                    P[cur ^ 1][t + q * kFsBlock] = acc;
                 }
-                P[cur ^ 1][e] = acc;
             }
             __syncthreads();
             cur ^= 1;
@@ -104,25 +138,33 @@ __global__ __launch_bounds__(kFsBlock) void k_fs_reduce(FsArgs a) {
 
 __global__ __launch_bounds__(kFsBlock) void k_fs_group(FsArgs a) {
     __shared__ double Q[2][kFsMaxD * kFsMaxD];
-    __shared__ double Pc[kFsMaxD * kFsMaxD];
+    __shared__ double Pb[kGroupLds / sizeof(double)];
     const int D = a.D, DD = D * D;
     const int t = threadIdx.x;
     const int g = blockIdx.x;
     const int c0 = g * kFsGroup;
     const int c1 = (c0 + kFsGroup < a.NC) ? c0 + kFsGroup : a.NC;
+    int nb = (int)(kGroupLds / sizeof(double)) / DD;
+    nb = nb < 1 ? 1 : nb;
     for (int e = t; e < DD; e += kFsBlock) Q[0][e] = (e / D == e % D) ? 0.0 : __builtin_inf();
     int cur = 0;
-    for (int c = c1 - 1; c >= c0; --c) {
+    // chunk products staged a batch at a time (every load in flight together)
+    for (int ce = c1; ce > c0; ce -= nb) {
+        const int cs = (ce - nb > c0) ? ce - nb : c0;
         __syncthreads();
-        for (int e = t; e < DD; e += kFsBlock) Pc[e] = a.P[(int64_t)c * DD + e];
+        stage_copy(Pb, a.P + (int64_t)cs * DD, (int64_t)(ce - cs) * DD, t, kFsBlock, Same{});
         __syncthreads();
-        for (int e = t; e < DD; e += kFsBlock) {
-            const int i = e / D, j = e - (e / D) * D;
-            double acc = __builtin_inf();
-            for (int m = 0; m < D; ++m) acc = fmin(acc, Pc[i * D + m] + Q[cur][m * D + j]);
-            Q[cur ^ 1][e] = acc;
+        for (int c = ce - 1; c >= cs; --c) {
+            const double* Pc = Pb + (c - cs) * DD;
+            for (int e = t; e < DD; e += kFsBlock) {
+                const int i = e / D, j = e - (e / D) * D;
+                double acc = __builtin_inf();
+                for (int m = 0; m < D; ++m) acc = fmin(acc, Pc[i * D + m] + Q[cur][m * D + j]);
+                Q[cur ^ 1][e] = acc;
+            }
+            __syncthreads();
+            cur ^= 1;
         }
-        cur ^= 1;
     }
     __syncthreads();
     for (int e = t; e < DD; e += kFsBlock) a.Q[(int64_t)g * DD + e] = Q[cur][e];
@@ -131,13 +173,17 @@ __global__ __launch_bounds__(kFsBlock) void k_fs_group(FsArgs a) {
 constexpr int kChainLds = 48 * 1024;  // LDS for a batch of matrices of a chain
 
 // Chain of min-plus matrix-vector products from V_end over the matrices
-// M_{hi-1}, ..., M_{lo} (consecutive, D*D each); lanes are states, V of lane j
-// by shuffle.  The matrices are staged into LDS a batch at a time (every load
-// of a batch in flight together, so the chain waits on memory once per
-// batch).  out[c] receives the value before matrix c for c in (lo, hi) and,
-// with out_lo, for c = lo.
+// M_{hi-1}, ..., M_{lo} (consecutive, D*D each); lanes are states.  The
+// matrices are staged into LDS a batch at a time (every load of a batch in
+// flight together, so the chain waits on memory once per batch), and each
+// product reads its row and the current V (broadcast) from LDS with every
+// read independent of the others.  out[c] receives the value before matrix c
+// for c in (lo, hi) and, with out_lo, for c = lo.
 __device__ __forceinline__ double fs_chain(const double* M, int lo, int hi, int D, int lane, double V,
                                            double* out, bool out_lo, double* lds) {
+    __shared__ double vsh[kFsMaxD];
+    __shared__ double ob[32 * kFsMaxD];  // values of the batch, stored after it (no global store
+                                         // may be outstanding at the barriers between products)
     const int DD = D * D;
     int nb = kChainLds / (int)sizeof(double) / DD;
     nb = nb < 1 ? 1 : (nb > 32 ? 32 : nb);
@@ -145,20 +191,27 @@ __device__ __forceinline__ double fs_chain(const double* M, int lo, int hi, int 
         const int cs = (ce - nb > lo) ? ce - nb : lo;
         __syncthreads();
         const double* src = M + (int64_t)cs * DD;
-        for (int e = lane; e < (ce - cs) * DD; e += kWaveFs) lds[e] = src[e];
+        stage_copy(lds, src, (int64_t)(ce - cs) * DD, lane, (int)blockDim.x, Same{});
         __syncthreads();
         for (int c = ce - 1; c >= cs; --c) {
             const double* row = lds + (c - cs) * DD + (lane < D ? lane : 0) * D;
+            if (lane < D) vsh[lane] = V;
+            __syncthreads();
             double acc = __builtin_inf();
-            for (int j = 0; j < D; ++j) acc = fmin(acc, row[j] + __shfl(V, j, kWaveFs));
+#pragma unroll
+            for (int j = 0; j < kFsMaxD; ++j)
+                if (j < D) acc = fmin(acc, row[j] + vsh[j]);
+            __syncthreads();
             V = lane < D ? acc : __builtin_inf();
-            if (lane < D && (c > lo || out_lo)) out[(int64_t)c * D + lane] = V;
+            if (lane < D) ob[(c - cs) * kFsMaxD + lane] = V;
         }
+        for (int c = cs; c < ce; ++c)
+            if (lane < D && (c > lo || out_lo)) out[(int64_t)c * D + lane] = ob[(c - cs) * kFsMaxD + lane];
     }
     return V;
 }
 
-__global__ __launch_bounds__(kWaveFs) void k_fs_top(FsArgs a) {
+__global__ __launch_bounds__(kFsBlock) void k_fs_top(FsArgs a) {
     __shared__ double lds[kChainLds / sizeof(double)];
     const int lane = threadIdx.x;
     const int D = a.D;
@@ -170,7 +223,7 @@ __global__ __launch_bounds__(kWaveFs) void k_fs_top(FsArgs a) {
     (void)fs_chain(a.Q, 0, a.NG, D, lane, V, a.gval, true, lds);
 }
 
-__global__ __launch_bounds__(kWaveFs) void k_fs_gdown(FsArgs a) {
+__global__ __launch_bounds__(kFsBlock) void k_fs_gdown(FsArgs a) {
     __shared__ double lds[kChainLds / sizeof(double)];
     const int lane = threadIdx.x;
     const int D = a.D;
@@ -295,10 +348,8 @@ __global__ __launch_bounds__(kWaveFs) void k_fs_fwd_final(FsArgs a) {
     int x = a.xs[c];
     for (int64_t kb = k0; kb < k1; kb += kFsStage) {
         const int S = (int)((k1 - kb < kFsStage) ? k1 - kb : kFsStage);
-        for (int e = lane; e < S * D; e += kWaveFs) {
-            nb[e] = a.nxt[kb * D + e];
-            ub[e] = a.ulaw[kb * D + e];
-        }
+        stage_copy(nb, a.nxt + kb * D, S * D, lane, kWaveFs, Same{});
+        stage_copy(ub, a.ulaw + kb * D, S * D, lane, kWaveFs, Same{});
         __syncthreads();
         if (lane == 0) {
             for (int j = 0; j < S; ++j) {
@@ -334,8 +385,8 @@ hipError_t fs_solve(const FsArgs& a, hipStream_t s, const StageHook* h) {
     };
     run("fs_reduce", [&] { k_fs_reduce<<<a.NC, kFsBlock, 0, s>>>(a); });
     run("fs_group", [&] { k_fs_group<<<a.NG, kFsBlock, 0, s>>>(a); });
-    run("fs_top", [&] { k_fs_top<<<1, kWaveFs, 0, s>>>(a); });
-    run("fs_gdown", [&] { k_fs_gdown<<<a.NG, kWaveFs, 0, s>>>(a); });
+    run("fs_top", [&] { k_fs_top<<<1, kFsBlock, 0, s>>>(a); });
+    run("fs_gdown", [&] { k_fs_gdown<<<a.NG, kFsBlock, 0, s>>>(a); });
     run("fs_final", [&] { k_fs_final<<<a.NC, kWaveFs, 0, s>>>(a); });
     if (a.x || a.ux || a.status) {
         run("fs_fwd_group", [&] { k_fs_fwd_group<<<a.NG, kWaveFs, 0, s>>>(a); });
