@@ -40,9 +40,9 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
 TRAFFIC = {
     ("bwd_final", "fp64", 1_000_000): {
-        "bytes_per_launch": 309_797_786,
-        "fetch_kib": 26486.4, "write_kib": 249564.1, "fetch_scale": 2.0, "write_scale": 1.0,
-        "src_sha256": "b69f3efbff9411da50cefba7e3106c635586ba00ef0a104ebf6027e841b0dc57",
+        "bytes_per_launch": 309_586_330,
+        "fetch_kib": 26486.5, "write_kib": 249357.4, "fetch_scale": 2.0, "write_scale": 1.0,
+        "src_sha256": "149f80ad099b208d26e1edf052a91d11c8f66566c9e014001ea6cb6b6c8d4daf",
     },
 }
 

@@ -127,7 +127,8 @@ struct NlArgs {
     int32_t f32;
 };
 hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipStream_t s);
-hipError_t nl_linearise(const NlArgs& g, hipStream_t s);
+// prev_change (nullable): the previous round's change word, completed here.
+hipError_t nl_linearise(const NlArgs& g, double* prev_change, hipStream_t s);
 hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s);
 hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s);
 

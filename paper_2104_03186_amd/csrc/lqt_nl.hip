@@ -12,69 +12,80 @@ namespace {
 
 constexpr int kNlBlock = 256;
 
-// One thread per step k: F_k = df/dx, L_k = df/du at (xbar_k, ubar_k),
-// c_k = f(xbar_k, ubar_k) - F_k xbar_k - L_k ubar_k, and a double copy of
-// ubar_k for the change measure.  Unicycle, x = (p_x, p_y, theta, s),
-// u = (a, w): f = (p_x + s cos(theta) dt, p_y + s sin(theta) dt, theta + w dt,
-// s + a dt).
-template <typename OT>
-__global__ __launch_bounds__(kNlBlock) void k_nl_linearise_unicycle(NlArgs g) {
-    const int64_t k = (int64_t)blockIdx.x * kNlBlock + threadIdx.x;
-    if (k >= g.T) return;
-    const OT* xb = (const OT*)g.x + k * 4;
-    const OT* ub = (const OT*)g.u + k * 2;
-    const double px = (double)xb[0], py = (double)xb[1], th = (double)xb[2], sp = (double)xb[3];
-    const double a = (double)ub[0], w = (double)ub[1];
-    const double dt = g.dt[k];
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    double F[16] = {1.0, 0.0, -sp * sn * dt, cs * dt,
-                    0.0, 1.0, sp * cs * dt, sn * dt,
-                    0.0, 0.0, 1.0, 0.0,
-                    0.0, 0.0, 0.0, 1.0};
-    double L[8] = {0.0, 0.0,
-                   0.0, 0.0,
-                   0.0, dt,
-                   dt, 0.0};
-    const double fx[4] = {px + sp * cs * dt, py + sp * sn * dt, th + w * dt, sp + a * dt};
-    const double xv[4] = {px, py, th, sp};
-    const double uv[2] = {a, w};
-    double* Fo = g.F + k * 16;
-    double* Lo = g.L + k * 8;
-    double* co = g.c + k * 4;
-    for (int i = 0; i < 4; ++i) {
-        double acc = fx[i];
-        for (int j = 0; j < 4; ++j) acc -= F[i * 4 + j] * xv[j];
-        for (int j = 0; j < 2; ++j) acc -= L[i * 2 + j] * uv[j];
-        co[i] = acc;
-    }
-    for (int i = 0; i < 16; ++i) Fo[i] = F[i];
-    for (int i = 0; i < 8; ++i) Lo[i] = L[i];
-    g.ubar[k * 2] = a;
-    g.ubar[k * 2 + 1] = w;
-}
-
-// max |u_new - ubar| over the horizon into *out (ordered as the bit patterns
-// of non-negative doubles; *out starts at zero).
-template <typename OT>
-__global__ __launch_bounds__(kNlBlock) void k_nl_change(NlArgs g, unsigned long long* out) {
+// Block maximum of v (all threads of the block call it) into *out, ordered
+// as the bit patterns of non-negative doubles (a NaN is reported as +inf).
+__device__ __forceinline__ void block_max_into(double v, unsigned long long* out) {
     __shared__ double sh[kNlBlock];
-    const OT* u = (const OT*)g.u;
-    const int64_t n = g.T * 2;
-    double mx = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kNlBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNlBlock)
-        mx = fmax(mx, fabs((double)u[i] - g.ubar[i]));
-    sh[threadIdx.x] = mx;
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int s = kNlBlock / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        // a NaN difference is reported as +inf
-        const double v = (sh[0] == sh[0]) ? sh[0] : __builtin_inf();
-        atomicMax(out, (unsigned long long)__double_as_longlong(v));
+        const double m = (sh[0] == sh[0]) ? sh[0] : __builtin_inf();
+        atomicMax(out, (unsigned long long)__double_as_longlong(m));
     }
+}
+
+// One thread per step k: F_k = df/dx, L_k = df/du at (xbar_k, ubar_k),
+// c_k = f(xbar_k, ubar_k) - F_k xbar_k - L_k ubar_k, and a double copy of
+// ubar_k for the change measure.  Unicycle, x = (p_x, p_y, theta, s),
+// u = (a, w): f = (p_x + s cos(theta) dt, p_y + s sin(theta) dt, theta + w dt,
+// s + a dt).  With prev (the previous round's change word), the previous
+// round's change max |ubar_k - copy_k| is folded in before the copy is
+// overwritten: the nominal of this round is the previous round's result.
+template <typename OT>
+__global__ __launch_bounds__(kNlBlock) void k_nl_linearise_unicycle(NlArgs g, unsigned long long* prev) {
+    const int64_t k = (int64_t)blockIdx.x * kNlBlock + threadIdx.x;
+    double diff = 0.0;
+    if (k < g.T) {
+        const OT* xb = (const OT*)g.x + k * 4;
+        const OT* ub = (const OT*)g.u + k * 2;
+        const double px = (double)xb[0], py = (double)xb[1], th = (double)xb[2], sp = (double)xb[3];
+        const double a = (double)ub[0], w = (double)ub[1];
+        const double dt = g.dt[k];
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        double F[16] = {1.0, 0.0, -sp * sn * dt, cs * dt,
+                        0.0, 1.0, sp * cs * dt, sn * dt,
+                        0.0, 0.0, 1.0, 0.0,
+                        0.0, 0.0, 0.0, 1.0};
+        double L[8] = {0.0, 0.0,
+                       0.0, 0.0,
+                       0.0, dt,
+                       dt, 0.0};
+        const double fx[4] = {px + sp * cs * dt, py + sp * sn * dt, th + w * dt, sp + a * dt};
+        const double xv[4] = {px, py, th, sp};
+        const double uv[2] = {a, w};
+        double* Fo = g.F + k * 16;
+        double* Lo = g.L + k * 8;
+        double* co = g.c + k * 4;
+        for (int i = 0; i < 4; ++i) {
+            double acc = fx[i];
+            for (int j = 0; j < 4; ++j) acc -= F[i * 4 + j] * xv[j];
+            for (int j = 0; j < 2; ++j) acc -= L[i * 2 + j] * uv[j];
+            co[i] = acc;
+        }
+        for (int i = 0; i < 16; ++i) Fo[i] = F[i];
+        for (int i = 0; i < 8; ++i) Lo[i] = L[i];
+        if (prev) diff = fmax(fabs(a - g.ubar[k * 2]), fabs(w - g.ubar[k * 2 + 1]));
+        g.ubar[k * 2] = a;
+        g.ubar[k * 2 + 1] = w;
+    }
+    if (prev) block_max_into(diff, prev);
+}
+
+// max |u_new - ubar| over the horizon into *out (ordered as the bit patterns
+// of non-negative doubles; *out starts at zero).
+template <typename OT>
+__global__ __launch_bounds__(kNlBlock) void k_nl_change(NlArgs g, unsigned long long* out) {
+    const OT* u = (const OT*)g.u;
+    const int64_t n = g.T * 2;
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNlBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNlBlock)
+        mx = fmax(mx, fabs((double)u[i] - g.ubar[i]));
+    block_max_into(mx, out);
 }
 
 // Zero `count` doubles (the change words and the round status words).
@@ -102,9 +113,10 @@ hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipSt
     return hipGetLastError();
 }
 
-hipError_t nl_linearise(const NlArgs& g, hipStream_t s) {
-    if (g.f32) k_nl_linearise_unicycle<float><<<grid_for(g.T), kNlBlock, 0, s>>>(g);
-    else k_nl_linearise_unicycle<double><<<grid_for(g.T), kNlBlock, 0, s>>>(g);
+hipError_t nl_linearise(const NlArgs& g, double* prev_change, hipStream_t s) {
+    unsigned long long* prev = (unsigned long long*)prev_change;
+    if (g.f32) k_nl_linearise_unicycle<float><<<grid_for(g.T), kNlBlock, 0, s>>>(g, prev);
+    else k_nl_linearise_unicycle<double><<<grid_for(g.T), kNlBlock, 0, s>>>(g, prev);
     return hipGetLastError();
 }
 

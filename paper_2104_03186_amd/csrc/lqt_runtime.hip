@@ -1000,18 +1000,19 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
     };
     if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
     for (int it = 0; it < iterations; ++it) {
+        // the change of round it - 1 is completed by this round's linearisation
         if (plan->prof.on) Profiler::begin(&plan->prof, "nl_linearise", s);
-        st = launched(lqt::nl_linearise(g, s));
+        st = launched(lqt::nl_linearise(g, (change && it > 0) ? change + it - 1 : nullptr, s));
         if (plan->prof.on) Profiler::end(&plan->prof, s);
         if (st != LQT_OK) return st;
         o.status = round_status + it;
         if ((st = solve_all(plan, plan->main, &p, &o, 1, s, nullptr)) != LQT_OK) return st;
-        if (change) {
-            if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
-            st = launched(lqt::nl_change(g, change + it, s));
-            if (plan->prof.on) Profiler::end(&plan->prof, s);
-            if (st != LQT_OK) return st;
-        }
+    }
+    if (change) {
+        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
+        st = launched(lqt::nl_change(g, change + iterations - 1, s));
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        if (st != LQT_OK) return st;
     }
     return launched(lqt::nl_finish(round_status, iterations, status, s));
 }
