@@ -307,8 +307,9 @@ typedef struct {
  * are caller-owned.  LQT_EINVAL (nothing enqueued): D_x or D_u outside
  * 1..32, T < 1, x0 outside 0..D_x-1, NULL tables, unknown per_step bits.
  * Next-state entries outside -1..D_x-1 are treated as not admissible.
- * Workspace: about (D_x^2 + 2 D_x) T / B doubles with B >= T / 256, plus
- * D_x T int32 (the closed-loop maps of every step). */
+ * Workspace: about (D_x^2 + 2 D_x) NC doubles for NC = min(2048, T / 16)
+ * blocks of consecutive steps, plus D_x T int32 (the closed-loop maps of
+ * every step) and, when u is NULL, D_x T int32 for the control law. */
 lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem *prob, const lqt_fs_outputs *out, void *stream);
 
 /* Wait for all work of the plan, then release it and its workspace. */
