@@ -414,11 +414,10 @@ def run_blocks(args, api, inputs, torch):
     dp = api.DeviceProblem(prob)
     do = api.DeviceOutputs(n, m, T)
     stream = torch.cuda.current_stream(0)
-    saved = os.environ.pop("LQT_CHUNK", None)
     res = {}
     try:
         for B in (1, 2, 4, 8, 12, 16, 24, 32, 64):
-            os.environ["LQT_CHUNK"] = str(B)
+            plan.set_routing(lane_chunk=B)
             for _ in range(2):
                 plan.solve([dp], [do], stream)
             torch.cuda.synchronize()
@@ -431,9 +430,6 @@ def run_blocks(args, api, inputs, torch):
             torch.cuda.synchronize()
             res[str(B)] = round(e0.elapsed_time(e1) / args.block_steps, 4)
     finally:
-        os.environ.pop("LQT_CHUNK", None)
-        if saved is not None:
-            os.environ["LQT_CHUNK"] = saved
         plan.close()
     best = min(res, key=res.get)
     return {"workload": f"block length sweep, tracking n=4 m=2 T={T} fp64", "ms_per_solve_by_block": res,

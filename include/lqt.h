@@ -191,6 +191,28 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_output
 lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
                     int32_t count, void *stream, int32_t *chosen);
 
+/* Routing and chunking overrides of one plan (testing, tuning and the
+ * block-length study of Section V-C).  They apply to the plan's later
+ * lqt_solve, lqt_tune, lqt_submit and lqt_nl_iterate calls; other plans are
+ * not affected.  Every field 0 selects the automatic choice:
+ *   path:       1 = the lane pipeline wherever it applies (nx <= 4, nu <= nx,
+ *               any T), 2 = the chunked engines for every instance;
+ *   block:      1 = instances of the size classes 16 and 32 stay on the
+ *               wavefront engine even when they are time-invariant;
+ *   lane_chunk: steps per lane of the lane pipeline, 1..1024;
+ *   wave_chunk: steps per chunk of the chunked engines, 1..4096 (takes
+ *               precedence over a tuned chunk length).
+ * The chunking changes only the association order of the scan.  NULL restores
+ * the automatic choices.  LQT_EINVAL for values outside these ranges. */
+typedef struct {
+    int32_t path;
+    int32_t block;
+    int32_t lane_chunk;
+    int32_t wave_chunk;
+} lqt_routing;
+
+lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing *routing);
+
 /* Serving interface (continuous batching).  lqt_submit queues one instance
  * and returns at once with *ticket.  Queued requests are launched in FIFO
  * order as batches: whenever one of the plan's serving streams is idle, the

@@ -22,7 +22,7 @@ PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
             "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate",
-            "lqt_fs_solve")
+            "lqt_fs_solve", "lqt_set_routing")
 
 _vp = ctypes.c_void_p
 
@@ -67,6 +67,11 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_nx", ctypes.c_int32), ("max_nu", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t), ("max_steps", ctypes.c_int64),
                 ("max_inflight", ctypes.c_int32), ("trajectory", ctypes.c_int32)]
+
+
+class Routing(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32), ("lane_chunk", ctypes.c_int32),
+                ("wave_chunk", ctypes.c_int32)]
 
 
 class ServeStats(ctypes.Structure):
@@ -119,6 +124,8 @@ def load() -> ctypes.CDLL:
     lib.lqt_nl_iterate.restype = ctypes.c_int
     lib.lqt_fs_solve.argtypes = [_vp, ctypes.POINTER(FSProblem), ctypes.POINTER(FSOutputs), _vp]
     lib.lqt_fs_solve.restype = ctypes.c_int
+    lib.lqt_set_routing.argtypes = [_vp, ctypes.POINTER(Routing)]
+    lib.lqt_set_routing.restype = ctypes.c_int
     lib.lqt_last_error.argtypes = [_vp]
     lib.lqt_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -26,17 +26,30 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hdrs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(CSRC, "*.inc"))
+    hdrs += glob.glob(os.path.join(ROOT, "include", "*.h"))
+    return max((os.path.getmtime(h) for h in hdrs), default=0.0)
+
+
+def _compile(src: str, force: bool, hdr_mtime: float) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(src) and t > hdr_mtime and t > os.path.getmtime(__file__):
+            return obj
     subprocess.check_call([HIPCC, *FLAGS, "-c", src, "-o", obj])
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only those older than their inputs
+    (any header counts as an input of every source), then link."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    hdr = _headers_mtime()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, force, hdr), srcs))
     tmp = LIB + f".tmp{os.getpid()}"
     subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
@@ -46,4 +59,6 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    import sys
+
+    build(verbose=True, force="--incremental" not in sys.argv[1:])

@@ -117,20 +117,21 @@ hipError_t gen_transform(const GenArgs& g, hipStream_t s);
 hipError_t gen_post(const GenArgs& g, hipStream_t s);
 
 // Iterated linearisation (the nonlinear extension of Section IV-D), unicycle model: one round's
-// expansion of the dynamics about the nominal (x, u: the plan's output type)
-// into per-step F, L, c, plus a double copy of the nominal controls.
+// expansion of the dynamics about the nominal (x, u, double) into per-step
+// F, L, c, plus a copy of the nominal controls for the change measure.
 struct NlArgs {
     const double* dt;
     int64_t T;
-    const void *x, *u;  // nominal trajectory [T+1][4], [T][2]
+    const double *x, *u;       // nominal trajectory [T+1][4], [T][2]
     double *F, *L, *c, *ubar;  // [T][4][4], [T][4][2], [T][4], [T][2]
-    int32_t f32;
 };
 hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipStream_t s);
 // prev_change (nullable): the previous round's change word, completed here.
 hipError_t nl_linearise(const NlArgs& g, double* prev_change, hipStream_t s);
 hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s);
 hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s);
+// dst[i] = src[i] for i < count, each side float (f32 set) or double.
+hipError_t nl_convert(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s);
 
 // Finite state and control spaces (Section III-D).  The horizon is cut into
 // NC <= kFsMaxNC chunks of B steps, the chunks into groups of kFsGroup.

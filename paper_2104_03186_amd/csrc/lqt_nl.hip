@@ -1,7 +1,8 @@
 // Iterated linearisation for nonlinear dynamics (the nonlinear extension of Section IV-D): the device
 // side of one round -- the first-order Taylor expansion of the dynamics about
 // the nominal trajectory, and the round's convergence measure.  Model: the
-// unicycle of the nonlinear experiment (Section VI-E).
+// unicycle of the nonlinear experiment (Section VI-E).  The nominal is held
+// in double on every plan (a MIXED plan converts at entry and exit).
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"
@@ -35,15 +36,14 @@ __device__ __forceinline__ void block_max_into(double v, unsigned long long* out
 // s + a dt).  With prev (the previous round's change word), the previous
 // round's change max |ubar_k - copy_k| is folded in before the copy is
 // overwritten: the nominal of this round is the previous round's result.
-template <typename OT>
 __global__ __launch_bounds__(kNlBlock) void k_nl_linearise_unicycle(NlArgs g, unsigned long long* prev) {
     const int64_t k = (int64_t)blockIdx.x * kNlBlock + threadIdx.x;
     double diff = 0.0;
     if (k < g.T) {
-        const OT* xb = (const OT*)g.x + k * 4;
-        const OT* ub = (const OT*)g.u + k * 2;
-        const double px = (double)xb[0], py = (double)xb[1], th = (double)xb[2], sp = (double)xb[3];
-        const double a = (double)ub[0], w = (double)ub[1];
+        const double* xb = g.x + k * 4;
+        const double* ub = g.u + k * 2;
+        const double px = xb[0], py = xb[1], th = xb[2], sp = xb[3];
+        const double a = ub[0], w = ub[1];
         const double dt = g.dt[k];
         double sn, cs;
         sincos(th, &sn, &cs);
@@ -78,13 +78,12 @@ __global__ __launch_bounds__(kNlBlock) void k_nl_linearise_unicycle(NlArgs g, un
 
 // max |u_new - ubar| over the horizon into *out (ordered as the bit patterns
 // of non-negative doubles; *out starts at zero).
-template <typename OT>
 __global__ __launch_bounds__(kNlBlock) void k_nl_change(NlArgs g, unsigned long long* out) {
-    const OT* u = (const OT*)g.u;
+    const double* u = g.u;
     const int64_t n = g.T * 2;
     double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kNlBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNlBlock)
-        mx = fmax(mx, fabs((double)u[i] - g.ubar[i]));
+        mx = fmax(mx, fabs(u[i] - g.ubar[i]));
     block_max_into(mx, out);
 }
 
@@ -103,6 +102,12 @@ __global__ void k_nl_status(const int32_t* st, int n, int32_t* out) {
     *out = v;
 }
 
+template <typename S, typename D>
+__global__ __launch_bounds__(kNlBlock) void k_nl_convert(const S* src, D* dst, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * kNlBlock + threadIdx.x;
+    if (i < count) dst[i] = (D)src[i];
+}
+
 unsigned grid_for(int64_t count) { return (unsigned)((count + kNlBlock - 1) / kNlBlock); }
 
 }  // namespace
@@ -115,16 +120,28 @@ hipError_t nl_start(double* change, int iterations, int32_t* round_status, hipSt
 
 hipError_t nl_linearise(const NlArgs& g, double* prev_change, hipStream_t s) {
     unsigned long long* prev = (unsigned long long*)prev_change;
-    if (g.f32) k_nl_linearise_unicycle<float><<<grid_for(g.T), kNlBlock, 0, s>>>(g, prev);
-    else k_nl_linearise_unicycle<double><<<grid_for(g.T), kNlBlock, 0, s>>>(g, prev);
+    k_nl_linearise_unicycle<<<grid_for(g.T), kNlBlock, 0, s>>>(g, prev);
     return hipGetLastError();
 }
 
 hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s) {
     if (!out) return hipSuccess;
     const unsigned grid = grid_for(g.T * 2) < 1024u ? grid_for(g.T * 2) : 1024u;
-    if (g.f32) k_nl_change<float><<<grid, kNlBlock, 0, s>>>(g, (unsigned long long*)out);
-    else k_nl_change<double><<<grid, kNlBlock, 0, s>>>(g, (unsigned long long*)out);
+    k_nl_change<<<grid, kNlBlock, 0, s>>>(g, (unsigned long long*)out);
+    return hipGetLastError();
+}
+
+hipError_t nl_convert(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned grid = grid_for(count);
+    if (src_f32 && !dst_f32)
+        k_nl_convert<float, double><<<grid, kNlBlock, 0, s>>>((const float*)src, (double*)dst, count);
+    else if (!src_f32 && dst_f32)
+        k_nl_convert<double, float><<<grid, kNlBlock, 0, s>>>((const double*)src, (float*)dst, count);
+    else if (src_f32)
+        k_nl_convert<float, float><<<grid, kNlBlock, 0, s>>>((const float*)src, (float*)dst, count);
+    else
+        k_nl_convert<double, double><<<grid, kNlBlock, 0, s>>>((const double*)src, (double*)dst, count);
     return hipGetLastError();
 }
 

@@ -33,35 +33,32 @@ constexpr int kServeSlots = 4;
 constexpr int kServeBatchMax = 512;
 constexpr int kDefaultQueue = 4096;
 
-// Path of an instance: a function of the instance alone (never of the batch),
-// so a result is the same alone and in any mix.  LQT_PATH=small|wave forces
-// one path where it applies (tests).
+// Path of an instance: a function of the instance and the plan's routing
+// overrides (never of the batch), so a result is the same alone and in any
+// mix.  Routing override 1 takes the lane pipeline wherever it applies, 2 the
+// chunked engines.
 enum class Path { Small, Wave };
 
-Path path_of(const lqt_problem& p) {
-    int force = 0;
-    if (const char* e = getenv("LQT_PATH")) force = !strcmp(e, "small") ? 1 : (!strcmp(e, "wave") ? 2 : 0);
+Path path_of(const lqt_routing& R, const lqt_problem& p) {
     const bool small_ok = lqt::small_supported(p.nx, p.nu);
-    if (force == 1 && small_ok) return Path::Small;
-    if (force == 2) return Path::Wave;
+    if (R.path == 1 && small_ok) return Path::Small;
+    if (R.path == 2) return Path::Wave;
     return (small_ok && p.T >= kSmallMinT) ? Path::Small : Path::Wave;
 }
 
 // Engine of a chunked-path instance: the workgroup engine (padded dimension
 // 16, 32 or 64) for time-invariant instances (only c and r may vary per step)
 // of the classes 16 and 32 and for every class-64 instance, else the
-// wavefront engine (0).  LQT_BLOCK=0 keeps the classes 16 and 32 on the
-// wavefront engine (tests).
+// wavefront engine (0).  Routing override block = 1 keeps the classes 16 and
+// 32 on the wavefront engine.
 int tile_class_of(const lqt_problem& p) {
     return lqt::tile_class(std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)));
 }
 
-int eng_of(const lqt_problem& p) {
+int eng_of(const lqt_routing& R, const lqt_problem& p) {
     const int cls = tile_class_of(p);
     if (cls == 64) return 64;
-    const char* e = getenv("LQT_BLOCK");
-    const bool allow = !(e && !strcmp(e, "0"));
-    if (allow && (cls == 16 || cls == 32) && !(p.per_step & ~(uint32_t)LQT_PS_c))
+    if (R.block != 1 && (cls == 16 || cls == 32) && !(p.per_step & ~(uint32_t)LQT_PS_c))
         return (cls == 32 && p.nu <= 16) ? lqt::kEng32m16 : cls;
     return 0;
 }
@@ -71,14 +68,12 @@ int eng_of(const lqt_problem& p) {
 // `div` chunks per instance for the launch group, at least 16 steps each
 // (div = 1: one chunk, no element fold at all -- the instance is then solved
 // by the sequential down-sweep alone, which pays when a batch has enough
-// instances to fill the GPU).  LQT_WCHUNK fixes the length (tests).
+// instances to fill the GPU).  The routing override wave_chunk fixes the
+// length.
 constexpr int kTuneDivs[] = {1, 4, 16, 64, 256};
 
-int wave_chunk(int64_t T, int div = 0) {
-    if (const char* e = getenv("LQT_WCHUNK")) {
-        int b = atoi(e);
-        if (b >= 1 && b <= 4096) return b;
-    }
+int wave_chunk(const lqt_routing& R, int64_t T, int div = 0) {
+    if (R.wave_chunk >= 1 && R.wave_chunk <= 4096) return R.wave_chunk;
     if (div <= 0) {
         const int64_t b = (T + 63) / 64;
         return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
@@ -89,10 +84,10 @@ int wave_chunk(int64_t T, int div = 0) {
 
 // Launch group of a chunked-path instance: size class (8, 16, 32, 64) and
 // engine (wavefront / workgroup), as an index 0..7.
-int group_key(const lqt_problem& p) {
+int group_key(const lqt_routing& R, const lqt_problem& p) {
     const int cls = tile_class_of(p);
     const int ci = cls <= 8 ? 0 : (cls <= 16 ? 1 : (cls <= 32 ? 2 : 3));
-    return 2 * ci + (eng_of(p) ? 1 : 0);
+    return 2 * ci + (eng_of(R, p) ? 1 : 0);
 }
 
 thread_local std::string g_create_error;
@@ -187,6 +182,7 @@ struct lqt_plan_s {
     uint64_t next_ticket = 1;
     lqt_serve_stats stats{};
     int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
+    lqt_routing route{};                          // routing and chunking overrides (lqt_set_routing)
     lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
     bool has_side = false;
     Arena nl;                // iterated linearisation: linearised model, nominal controls, round status
@@ -210,11 +206,8 @@ lqt_status fail(lqt_plan_t p, lqt_status code, const char* fmt, ...) {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int chunk_length(int64_t T) {
-    if (const char* e = getenv("LQT_CHUNK")) {
-        int b = atoi(e);
-        if (b >= 1 && b <= 1024) return b;
-    }
+int chunk_length(const lqt_routing& R, int64_t T) {
+    if (R.lane_chunk >= 1 && R.lane_chunk <= 1024) return R.lane_chunk;
     // About 64K lanes (one wavefront per SIMD on 256 CUs), at most 16 steps
     // per lane; measured best for the n = 4 pipeline at T = 1e6.
     int64_t b = (T + 65535) / 65536;
@@ -230,12 +223,12 @@ struct Layout {
 
 // m2: forward pass by prefixes (Method 2), which reads S and v (scratch when
 // the caller does not take them).
-Layout layout_for(const lqt_problem& p, bool need_K, bool need_d, bool m2 = false, bool need_S = false,
-                  bool need_v = false) {
+Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool need_d, bool m2 = false,
+                  bool need_S = false, bool need_v = false) {
     using namespace lqt;
     Layout L{};
     const int n = p.nx, m = p.nu;
-    L.B = chunk_length(p.T);
+    L.B = chunk_length(R, p.T);
     L.NC = (p.T + L.B - 1) / L.B;
     L.NG = (int)((L.NC + 63) / 64);
     L.NB = (L.NG + lqt::kSmallTopBlock - 1) / lqt::kSmallTopBlock;
@@ -268,7 +261,7 @@ Layout layout_for(const lqt_problem& p, bool need_K, bool need_d, bool m2 = fals
 }
 
 int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
-    return wave_chunk(p.T, plan ? plan->tune_div[group_key(p)] : 0);
+    return wave_chunk(plan->route, p.T, plan->tune_div[group_key(plan->route, p)]);
 }
 
 // Workspace of one wavefront-path instance, and of its K, d scratch when the
@@ -276,7 +269,8 @@ int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
 size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
     const int B = chunk_for(plan, p);
     const int64_t NC = (p.T + B - 1) / B;
-    return align_up((size_t)lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(p), NC, B, p.c != nullptr) * sizeof(double));
+    const int64_t wd = lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(plan->route, p), NC, B, p.c != nullptr);
+    return align_up((size_t)wd * sizeof(double));
 }
 size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
     return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
@@ -319,9 +313,9 @@ struct BatchSize {
     void add(const lqt_problem& p0, const lqt_outputs& o) {
         gen += gen_bytes(p0, o);
         const lqt_problem p = std_shape(p0);
-        if (path_of(p) == Path::Small) {
+        if (path_of(plan->route, p) == Path::Small) {
             const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && (o.x || o.u);
-            small = std::max(small, align_up(layout_for(p, !o.K, !o.d, m2, !o.S, !o.v).total));
+            small = std::max(small, align_up(layout_for(plan->route, p, !o.K, !o.d, m2, !o.S, !o.v).total));
         } else {
             wave += wave_bytes(plan, p) + wave_kd_bytes(p, o);
             ++nwave;
@@ -338,11 +332,11 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
-    if (plan->desc.trajectory == LQT_TRAJ_PREFIX && path_of(p) != Path::Small && (o.x || o.u))
+    if (plan->desc.trajectory == LQT_TRAJ_PREFIX && path_of(plan->route, p) != Path::Small && (o.x || o.u))
         return fail(plan, LQT_ENOTSUP,
                     "instance %d: the forward-prefix trajectory is provided on the n <= 4 lane pipeline only "
                     "(nx=%d nu=%d T=%lld)", idx, p.nx, p.nu, (long long)p.T);
-    if (path_of(p) == Path::Wave) {
+    if (path_of(plan->route, p) == Path::Wave) {
         if (std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
             return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
                         p.nu, p.ny, p.nyT, kWaveMaxN);
@@ -399,11 +393,11 @@ lqt_status ensure_ws(lqt_plan_t plan, Arena& A, size_t bytes) {
 }
 
 lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const lqt_outputs& o, hipStream_t s,
-                      int32_t* status_override) {
+                      int32_t* status_override, bool f32) {
     const bool fwd = o.x || o.u;
     const bool need_K = !o.K, need_d = !o.d;
     const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && fwd;
-    Layout L = layout_for(p, need_K, need_d, m2, !o.S, !o.v);
+    Layout L = layout_for(plan->route, p, need_K, need_d, m2, !o.S, !o.v);
     lqt::SmallArgs a{};
     a.F = p.F; a.c = p.c; a.L = p.L; a.U = p.U; a.H = p.H; a.X = p.X; a.r = p.r;
     a.HT = p.HT; a.XT = p.XT; a.rT = p.rT; a.x0 = p.x0;
@@ -414,7 +408,7 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.K = o.K ? o.K : (void*)(base + L.K);
     a.d = o.d ? o.d : (void*)(base + L.d);
     a.x = o.x; a.u = o.u;
-    a.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
+    a.f32 = f32 ? 1 : 0;
     a.status = status_override ? status_override : o.status;
     a.cst = (double*)(base + L.cst);
     a.der = (double*)(base + L.der);
@@ -439,14 +433,17 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
 
 // Solve a set of instances on stream s in arena A.  status_override (if not
 // null) gives per-instance device status words used instead of outs[i].status.
+// Results are float when f32 is set (the plan's precision unless the caller
+// says otherwise), else double.
 lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const lqt_outputs* outs, int32_t count,
-                     hipStream_t s, int32_t* const* status_override) {
+                     hipStream_t s, int32_t* const* status_override, int f32_override = -1) {
+    const bool f32 = f32_override < 0 ? plan->desc.prec == LQT_PREC_MIXED : f32_override != 0;
     // partition by path; wavefront instances ordered by size class
     std::vector<int> small, wave;
-    for (int i = 0; i < count; ++i) (path_of(probs[i]) == Path::Small ? small : wave).push_back(i);
+    for (int i = 0; i < count; ++i) (path_of(plan->route, probs[i]) == Path::Small ? small : wave).push_back(i);
     // launch groups: (size class, engine)
     auto cls = [&](int i) {
-        const int e = eng_of(probs[i]);
+        const int e = eng_of(plan->route, probs[i]);
         return 4 * tile_class_of(probs[i]) + (e == 0 ? 0 : (e == lqt::kEng32m16 ? 2 : 1));
     };
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
@@ -488,7 +485,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
                 off += align_up((size_t)(p.T + 1) * p.nx * sizeof(double));
             }
             g.K = to[i].K; g.d = to[i].d; g.u = to[i].u; g.x = to[i].x;
-            g.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
+            g.f32 = f32 ? 1 : 0;
             tp[i].F = g.Ft; tp[i].c = g.ct; tp[i].X = g.Xt;
             tp[i].per_step |= LQT_PS_c;
             tp[i].M = nullptr;
@@ -513,7 +510,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     };
     char* const base = A.ws + bs.gen;
     for (int i : small) {
-        st = launch_one(plan, base, probs[i], outs[i], s, status_override ? status_override[i] : nullptr);
+        st = launch_one(plan, base, probs[i], outs[i], s, status_override ? status_override[i] : nullptr, f32);
         if (st != LQT_OK) return st;
     }
     if (wave.empty()) return post();
@@ -552,7 +549,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         g.chunk0 = chunk0;
         chunk0 += g.NC;
         g.ws = (double*)(wbase + ws_off[j]);
-        g.eng = eng_of(p);
+        g.eng = eng_of(plan->route, p);
         want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
     }
     lqt::GInst* d_inst = (lqt::GInst*)(wbase + bs.wave);
@@ -574,8 +571,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
             ++j1;
         }
         const lqt_problem& p0 = probs[wave[j0]];
-        const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
-        const int eng = eng_of(p0);
+        const int eng = eng_of(plan->route, p0);
         hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, f32, s,
                                               plan->prof.on ? &hook : nullptr)
                            : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
@@ -642,31 +638,63 @@ void pool_give(lqt_plan_t plan, size_t off, size_t len) {
     }
 }
 
+void slot_release(Slot& s) {
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.status_dev) (void)hipFree(s.status_dev);
+    if (s.status_host) (void)hipHostFree(s.status_host);
+    arena_release(s.arena);
+    s = Slot{};
+}
+
+// All or nothing: the pool and every slot exist afterwards, or none of them
+// (plan->pool is set last, so a failed set-up is retried by the next submit).
 lqt_status serve_init(lqt_plan_t plan) {
     if (plan->pool) return LQT_OK;
     const size_t want = plan->desc.hbm_budget_bytes ? plan->desc.hbm_budget_bytes : kDefaultServePool;
-    void* p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(plan, LQT_ENOMEM, "hipMalloc of the %zu-byte serving pool failed", want);
-    }
-    plan->pool = (char*)p;
-    plan->pool_size = want;
-    plan->free_ranges.clear();
-    plan->free_ranges[0] = want;
-    plan->stats.pool_bytes = want;
-    plan->slots.resize(kServeSlots);
-    for (Slot& s : plan->slots) {
+    std::vector<Slot> slots(kServeSlots);
+    bool ok = true;
+    for (Slot& s : slots) {
         s.arena.owned = false;
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
             hipMalloc(&s.status_dev, kServeBatchMax * sizeof(int32_t)) != hipSuccess ||
             hipHostMalloc((void**)&s.status_host, kServeBatchMax * sizeof(int32_t), 0) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(plan, LQT_EHIP, "serving slot set-up failed");
+            ok = false;
+            break;
         }
     }
+    void* p = nullptr;
+    if (ok && hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        for (Slot& s : slots) slot_release(s);
+        return fail(plan, LQT_ENOMEM, "hipMalloc of the %zu-byte serving pool failed", want);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        for (Slot& s : slots) slot_release(s);
+        return fail(plan, LQT_EHIP, "serving slot set-up failed");
+    }
+    plan->slots = std::move(slots);
+    plan->pool_size = want;
+    plan->free_ranges.clear();
+    plan->free_ranges[0] = want;
+    plan->stats.pool_bytes = want;
+    plan->pool = (char*)p;
     return LQT_OK;
+}
+
+// Give a slot's batch back: its requests' final states (`code` for all of
+// them, or the copied status words when code < 0), its pool range, the slot.
+void slot_retire(lqt_plan_t plan, Slot& s, int code) {
+    for (size_t i = 0; i < s.tickets.size(); ++i) plan->state[s.tickets[i]] = code < 0 ? s.status_host[i] : code;
+    plan->live -= s.tickets.size();
+    plan->stats.completed += (int64_t)s.tickets.size();
+    plan->stats.running_batches -= 1;
+    plan->stats.pool_in_use -= s.len;
+    s.tickets.clear();
+    pool_give(plan, s.off, s.len);
+    s.busy = false;
 }
 
 // Retire finished batches, then launch queued requests on idle slots.
@@ -678,19 +706,20 @@ lqt_status serve_pump(lqt_plan_t plan) {
             (void)hipGetLastError();
             continue;
         }
-        if (q != hipSuccess) return fail(plan, LQT_EHIP, "serving batch failed: %s", hipGetErrorString(q));
-        for (size_t i = 0; i < s.tickets.size(); ++i) plan->state[s.tickets[i]] = s.status_host[i];
-        plan->live -= s.tickets.size();
-        plan->stats.completed += (int64_t)s.tickets.size();
-        plan->stats.running_batches -= 1;
-        plan->stats.pool_in_use -= s.len;
-        s.tickets.clear();
-        pool_give(plan, s.off, s.len);
-        s.busy = false;
+        if (q != hipSuccess) {
+            // the batch's outcome is unknown: its requests fail, and its
+            // range is reused only once nothing queued on the stream runs
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s.stream);
+            (void)hipGetLastError();
+            slot_retire(plan, s, LQT_EHIP);
+            return fail(plan, LQT_EHIP, "serving batch failed: %s", hipGetErrorString(q));
+        }
+        slot_retire(plan, s, -1);
     }
     for (Slot& s : plan->slots) {
         if (plan->pending.empty()) break;
-        if (s.busy) continue;
+        if (s.busy || !s.stream || !s.done || !s.status_dev || !s.status_host) continue;
         const size_t room = pool_largest(plan);
         BatchSize bs(plan);
         size_t take = 0;
@@ -738,7 +767,15 @@ lqt_status serve_pump(lqt_plan_t plan) {
                 st = fail(plan, LQT_EHIP, "status copy failed");
         if (st == LQT_OK && hipEventRecord(s.done, s.stream) != hipSuccess)
             st = fail(plan, LQT_EHIP, "event record failed");
-        if (st != LQT_OK) return st;
+        if (st != LQT_OK) {
+            // part of the batch may be queued: wait for it before the range
+            // is reused, and report the launch failure for every request
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s.stream);
+            (void)hipGetLastError();
+            slot_retire(plan, s, st);
+            return st;
+        }
     }
     return LQT_OK;
 }
@@ -797,12 +834,12 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
             for (int m = 1; m <= desc->max_nu; ++m)
                 if (lqt::small_supported(n, m)) {
                     probe.nx = n; probe.nu = m; probe.ny = n;
-                    need = std::max(need, layout_for(probe, true, true, desc->trajectory == LQT_TRAJ_PREFIX,
-                                                     true, true).total);
+                    need = std::max(need, layout_for(p->route, probe, true, true,
+                                                     desc->trajectory == LQT_TRAJ_PREFIX, true, true).total);
                 }
         // and for one wavefront-path instance of the largest dimensions
         {
-            const int64_t B = wave_chunk(desc->max_steps);
+            const int64_t B = wave_chunk(p->route, desc->max_steps);
             const int64_t NC = (desc->max_steps + B - 1) / B;
             const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
             const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC),
@@ -862,7 +899,7 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
         std::vector<lqt_problem> ps;
         std::vector<lqt_outputs> os;
         for (int i = 0; i < count; ++i)
-            if (path_of(probs[i]) == Path::Wave && group_key(probs[i]) == key) {
+            if (path_of(plan->route, probs[i]) == Path::Wave && group_key(plan->route, probs[i]) == key) {
                 ps.push_back(probs[i]);
                 os.push_back(outs[i]);
             }
@@ -893,6 +930,23 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
     if (chosen)
         for (int key = 0; key < 8; ++key) chosen[key] = plan->tune_div[key];
     return st;
+}
+
+lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing* routing) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_set_routing: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (!routing) {
+        plan->route = lqt_routing{};
+        return LQT_OK;
+    }
+    const lqt_routing& r = *routing;
+    if (r.path < 0 || r.path > 2 || r.block < 0 || r.block > 1 || r.lane_chunk < 0 || r.lane_chunk > 1024 ||
+        r.wave_chunk < 0 || r.wave_chunk > 4096)
+        return fail(plan, LQT_EINVAL, "lqt_set_routing: path=%d block=%d lane_chunk=%d wave_chunk=%d out of range",
+                    r.path, r.block, r.lane_chunk, r.wave_chunk);
+    plan->route = r;
+    return LQT_OK;
 }
 
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, uint64_t* ticket) {
@@ -979,26 +1033,38 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
     lqt_status st = validate(plan, p, o, 0);
     if (st != LQT_OK) return st;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    // A MIXED plan iterates in double: the nominal trajectory of every round
+    // is kept in double workspace (xd, ud), each round is solved with double
+    // results, and only the last round's x and u are rounded to float.
+    const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
     const size_t model = align_up((size_t)T * (n * n + n * m + n + m) * sizeof(double));
-    st = ensure_ws(plan, plan->nl, model + align_up((size_t)iterations * sizeof(int32_t)));
+    const size_t nominal = f32 ? align_up((size_t)((T + 1) * n + T * m) * sizeof(double)) : 0;
+    st = ensure_ws(plan, plan->nl, model + nominal + align_up((size_t)iterations * sizeof(int32_t)));
     if (st != LQT_OK) return st;
     lqt::NlArgs g{};
     g.dt = prob->dt;
     g.T = T;
-    g.x = x;
-    g.u = u;
     g.F = (double*)plan->nl.ws;
     g.L = g.F + (size_t)T * n * n;
     g.c = g.L + (size_t)T * n * m;
     g.ubar = g.c + (size_t)T * n;
-    g.f32 = plan->desc.prec == LQT_PREC_MIXED ? 1 : 0;
-    int32_t* round_status = (int32_t*)(plan->nl.ws + model);
+    double* xd = f32 ? (double*)(plan->nl.ws + model) : nullptr;
+    double* ud = f32 ? xd + (size_t)(T + 1) * n : nullptr;
+    g.x = f32 ? xd : (const double*)x;
+    g.u = f32 ? ud : (const double*)u;
+    int32_t* round_status = (int32_t*)(plan->nl.ws + model + nominal);
     p.F = g.F; p.L = g.L; p.c = g.c;
+    o.x = f32 ? (void*)xd : x;
+    o.u = f32 ? (void*)ud : u;
     hipStream_t s = (hipStream_t)stream;
     auto launched = [&](hipError_t e) -> lqt_status {
         return e == hipSuccess ? LQT_OK : fail(plan, LQT_EHIP, "launch failed: %s", hipGetErrorString(e));
     };
     if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
+    if (f32) {
+        if ((st = launched(lqt::nl_convert(x, true, xd, false, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::nl_convert(u, true, ud, false, T * m, s))) != LQT_OK) return st;
+    }
     for (int it = 0; it < iterations; ++it) {
         // the change of round it - 1 is completed by this round's linearisation
         if (plan->prof.on) Profiler::begin(&plan->prof, "nl_linearise", s);
@@ -1006,13 +1072,17 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
         if (plan->prof.on) Profiler::end(&plan->prof, s);
         if (st != LQT_OK) return st;
         o.status = round_status + it;
-        if ((st = solve_all(plan, plan->main, &p, &o, 1, s, nullptr)) != LQT_OK) return st;
+        if ((st = solve_all(plan, plan->main, &p, &o, 1, s, nullptr, 0)) != LQT_OK) return st;
     }
     if (change) {
         if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
         st = launched(lqt::nl_change(g, change + iterations - 1, s));
         if (plan->prof.on) Profiler::end(&plan->prof, s);
         if (st != LQT_OK) return st;
+    }
+    if (f32) {
+        if ((st = launched(lqt::nl_convert(xd, false, x, true, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::nl_convert(ud, false, u, true, T * m, s))) != LQT_OK) return st;
     }
     return launched(lqt::nl_finish(round_status, iterations, status, s));
 }
@@ -1073,13 +1143,7 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
     if (!plan) return LQT_OK;
     (void)hipSetDevice(plan->desc.device);
     (void)hipDeviceSynchronize();
-    for (Slot& s : plan->slots) {
-        if (s.stream) (void)hipStreamDestroy(s.stream);
-        if (s.done) (void)hipEventDestroy(s.done);
-        if (s.status_dev) (void)hipFree(s.status_dev);
-        if (s.status_host) (void)hipHostFree(s.status_host);
-        arena_release(s.arena);
-    }
+    for (Slot& s : plan->slots) slot_release(s);
     if (plan->pool) (void)hipFree(plan->pool);
     if (plan->has_side) {
         (void)hipStreamDestroy(plan->side.side);

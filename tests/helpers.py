@@ -1,4 +1,5 @@
-"""Shared test helpers: relative errors and a brute-force KKT solver.
+"""Shared test helpers: relative errors (stacked and per step) and a brute-force
+KKT solver.
 
 The KKT solver is independent of the oracle: it assembles the equality-
 constrained quadratic program of the LQT problem statement (Section II-B of the
@@ -18,6 +19,34 @@ def rel(a, b):
     if nb == 0.0:
         return float(np.linalg.norm(a))
     return float(np.linalg.norm(a - b) / nb)
+
+
+def step_rel(a, b):
+    """Largest per-step relative error, time on the first axis:
+    max_k ||a_k - b_k|| / max(||b_k||, rms), rms = sqrt(mean_k ||b_k||^2).
+
+    Each step is held to its own size, or to the RMS step size where the step
+    is smaller than that (a step near zero is not divided by its own tiny
+    norm).  The stacked norm of rel() spreads one wrong step over all T of
+    them (one bad step at T = 1e6 moves it by 1/1000 of that step's error);
+    this one does not.  Where no step exceeds the RMS size it is never below
+    rel()."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.ndim == 0 or a.shape[0] == 0:
+        return rel(a, b)
+    d = np.linalg.norm((a - b).reshape(a.shape[0], -1), axis=1)
+    nb = np.linalg.norm(b.reshape(b.shape[0], -1), axis=1)
+    rms = float(np.sqrt(np.mean(nb ** 2)))
+    if rms == 0.0:
+        return float(np.max(d))
+    return float(np.max(d / np.maximum(nb, rms)))
+
+
+def err(a, b):
+    """Parity gate of the GPU tests: the larger of the stacked relative error
+    and the per-step error (step_rel), so every step is held to the bound."""
+    return max(rel(a, b), step_rel(a, b))
 
 
 def _mat(prob, name, bit, k):

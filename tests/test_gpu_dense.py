@@ -2,10 +2,10 @@
 against the FP64 oracle: dense SPD costs, zero-padding edge cases, per-step
 offsets, the full dense batch shape, and batch independence.
 
-Tolerance: relative Frobenius error per output family, 1e-10 (FP64) and
-1e-5 (MIXED).
+Tolerance: relative error per output family, over all steps stacked (Frobenius) and
+per step (largest step error against the RMS step size; tests/helpers.err),
+1e-10 (FP64) and 1e-5 (MIXED).
 """
-import os
 import sys
 
 import numpy as np
@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2104_03186_amd import inputs
-from tests.helpers import FAMILIES, rel
+from tests.helpers import FAMILIES, err
 
 pytestmark = pytest.mark.gpu
 
@@ -44,22 +44,16 @@ def plans(api):
 
 
 @pytest.fixture(autouse=True)
-def _env():
-    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_CHUNK", "LQT_PATH")}
+def _routing(plans):
     yield
-    for k in saved:
-        os.environ.pop(k, None)
-        if saved[k] is not None:
-            os.environ[k] = saved[k]
+    for p in plans.values():
+        p.set_routing()
 
 
 def run(api, plan, probs, prec, want=FAMILIES, chunk=None):
     import torch
 
-    if chunk is not None:
-        os.environ["LQT_WCHUNK"] = str(chunk)
-    else:
-        os.environ.pop("LQT_WCHUNK", None)
+    plan.set_routing(wave_chunk=chunk or 0)
     dt = torch.float64 if prec == "fp64" else torch.float32
     dps = [api.DeviceProblem(p) for p in probs]
     dos = [api.DeviceOutputs(p.n, p.m, p.T, want=want, dtype=dt) for p in probs]
@@ -69,7 +63,7 @@ def run(api, plan, probs, prec, want=FAMILIES, chunk=None):
 
 
 def check(got, ref, tol):
-    errs = {f: rel(got[f], ref[f]) for f in got}
+    errs = {f: err(got[f], ref[f]) for f in got}
     bad = {f: e for f, e in errs.items() if not e <= tol}
     assert not bad, f"rel errors above {tol}: {bad} (all: {errs})"
     return errs

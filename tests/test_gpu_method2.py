@@ -4,10 +4,10 @@ closed-loop-map trajectory (Method 1) of the same backward pass; FP64 and
 MIXED; default and forced chunk lengths; time-varying data; outputs without
 S and v (library workspace); the LQT_ENOTSUP boundary for other paths.
 
-Tolerance: relative Frobenius error per output family, 1e-10 (FP64) and
-1e-5 (MIXED).
+Tolerance: relative error per output family, over all steps stacked (Frobenius) and
+per step (largest step error against the RMS step size; tests/helpers.err),
+1e-10 (FP64) and 1e-5 (MIXED).
 """
-import os
 import sys
 
 import numpy as np
@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2104_03186_amd import inputs
-from tests.helpers import FAMILIES, rel
+from tests.helpers import FAMILIES, err
 
 pytestmark = pytest.mark.gpu
 
@@ -47,23 +47,18 @@ def plans(api):
 
 
 @pytest.fixture(autouse=True)
-def _env():
-    saved = {k: os.environ.pop(k, None) for k in ("LQT_CHUNK", "LQT_PATH")}
-    os.environ["LQT_PATH"] = "small"
+def _routing(plans):
     yield
-    for k, v in saved.items():
-        os.environ.pop(k, None)
-        if v is not None:
-            os.environ[k] = v
+    for p in plans.values():
+        p.set_routing()
 
 
-def run(api, plan, prob, prec, want=FAMILIES, chunk=None):
+def run(api, plan, prob, prec, want=FAMILIES, chunk=None, path="small"):
+    """Solve on the lane pipeline (path "small", any T) unless path says
+    otherwise; chunk fixes the steps per lane."""
     import torch
 
-    if chunk is not None:
-        os.environ["LQT_CHUNK"] = str(chunk)
-    else:
-        os.environ.pop("LQT_CHUNK", None)
+    plan.set_routing(path=path, lane_chunk=chunk or 0)
     dt = torch.float64 if prec == "fp64" else torch.float32
     dp = api.DeviceProblem(prob)
     do = api.DeviceOutputs(prob.n, prob.m, prob.T, want=want, dtype=dt)
@@ -81,13 +76,13 @@ def test_prefix_trajectory(api, plans, prec, T, chunk):
     prob = inputs.tracking_problem(n=4, m=2, T=T, instance=3)
     got = run(api, plans[(prec, "prefix")], prob, prec, chunk=chunk)
     ref = oracle.solve(prob)
-    errs = {f: rel(got[f], ref[f]) for f in FAMILIES}
+    errs = {f: err(got[f], ref[f]) for f in FAMILIES}
     assert max(errs.values()) <= TOL[prec], errs
     alt = run(api, plans[(prec, "maps")], prob, prec, chunk=chunk)
     for f in ("S", "v", "K", "d"):  # same backward pass
         assert np.array_equal(got[f], alt[f]), f
     for f in ("x", "u"):
-        assert rel(got[f], alt[f]) <= TOL[prec], (f, rel(got[f], alt[f]))
+        assert err(got[f], alt[f]) <= TOL[prec], (f, err(got[f], alt[f]))
 
 
 @pytest.mark.parametrize("nm", [(1, 1), (2, 2), (3, 1), (4, 1), (4, 3), (4, 4)])
@@ -100,7 +95,7 @@ def test_prefix_shapes_and_time_varying(api, plans, nm, per_step):
                                  scale=0.95)
     got = run(api, plans[("fp64", "prefix")], prob, "fp64", chunk=7)
     ref = oracle.solve(prob)
-    errs = {f: rel(got[f], ref[f]) for f in FAMILIES}
+    errs = {f: err(got[f], ref[f]) for f in FAMILIES}
     assert max(errs.values()) <= TOL["fp64"], errs
 
 
@@ -113,7 +108,7 @@ def test_prefix_without_value_outputs(api, plans, want):
     assert set(got) == set(want)
     ref = oracle.solve(prob)
     for f in want:
-        assert rel(got[f], ref[f]) <= TOL["fp64"], f
+        assert err(got[f], ref[f]) <= TOL["fp64"], f
 
 
 def test_prefix_full_size(api, plans):
@@ -122,14 +117,13 @@ def test_prefix_full_size(api, plans):
     prob = inputs.tracking_problem(n=4, m=2, T=T, workload=1)
     got = run(api, plans[("fp64", "prefix")], prob, "fp64")
     ref = oracle.solve(prob)
-    errs = {f: rel(got[f], ref[f]) for f in FAMILIES}
+    errs = {f: err(got[f], ref[f]) for f in FAMILIES}
     assert max(errs.values()) <= TOL["fp64"], errs
 
 
 def test_prefix_limits(api):
     from paper_2104_03186_amd import _lib
 
-    os.environ.pop("LQT_PATH", None)
     plan = api.Plan(8, 4, prec="fp64", trajectory="prefix")
     try:
         prob = inputs.random_problem(6, 3, 50, seed=9)  # wavefront path
@@ -141,6 +135,6 @@ def test_prefix_limits(api):
         got = run(api, plan, prob, "fp64", want=("S", "v", "K", "d"))
         ref = oracle.solve(prob)
         for f in ("S", "v", "K", "d"):
-            assert rel(got[f], ref[f]) <= TOL["fp64"], f
+            assert err(got[f], ref[f]) <= TOL["fp64"], f
     finally:
         plan.close()

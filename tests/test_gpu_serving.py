@@ -5,7 +5,6 @@ Every served result is checked against the FP64 oracle (MIXED tolerance
 1e-5) and against the same instance solved alone by lqt_solve, bit for bit:
 batching must never change a result.
 """
-import os
 import sys
 import time
 
@@ -14,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2104_03186_amd import inputs
-from tests.helpers import FAMILIES, rel
+from tests.helpers import FAMILIES, err
 
 pytestmark = pytest.mark.gpu
 
@@ -34,15 +33,6 @@ def api():
     from paper_2104_03186_amd import api as _api
 
     return _api
-
-
-@pytest.fixture(autouse=True)
-def _env():
-    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_CHUNK", "LQT_PATH")}
-    yield
-    for k in saved:
-        if saved[k] is not None:
-            os.environ[k] = saved[k]
 
 
 def served_request(n, T, i):
@@ -82,7 +72,7 @@ def solve_alone(api, p):
 
 
 def check(got, ref):
-    errs = {f: rel(got[f], ref[f]) for f in got}
+    errs = {f: err(got[f], ref[f]) for f in got}
     bad = {f: e for f, e in errs.items() if not e <= TOL}
     assert not bad, f"rel errors above {TOL}: {bad}"
 

@@ -1,7 +1,6 @@
 """GPU test of the chunk-length autotuner (lqt_tune): the chosen lengths come
 from the candidate set, results of the tuned plan stay within the FP64
 tolerance of the oracle, and a result is the same alone and in a batch."""
-import os
 import sys
 
 import numpy as np
@@ -9,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2104_03186_amd import inputs
-from tests.helpers import FAMILIES, rel
+from tests.helpers import FAMILIES, err
 
 pytestmark = pytest.mark.gpu
 
@@ -19,15 +18,6 @@ TOL = 1e-10
 def _say(*a):
     print("[case]", *a, flush=True)
     sys.stdout.flush()
-
-
-@pytest.fixture(autouse=True)
-def _env():
-    saved = {k: os.environ.pop(k, None) for k in ("LQT_WCHUNK", "LQT_CHUNK", "LQT_PATH", "LQT_BLOCK")}
-    yield
-    for k in saved:
-        if saved[k] is not None:
-            os.environ[k] = saved[k]
 
 
 def test_tuned_plan():
@@ -54,7 +44,7 @@ def test_tuned_plan():
         assert int(do.status.item()) == 0
         got = do.host()
         ref = oracle.solve(p)
-        errs = {f: rel(got[f], ref[f]) for f in FAMILIES}
+        errs = {f: err(got[f], ref[f]) for f in FAMILIES}
         assert max(errs.values()) <= TOL, (i, errs)
         if i % 3 == 0:
             alone = api.DeviceOutputs(p.n, p.m, p.T)
