@@ -131,7 +131,7 @@ hipError_t nl_linearise(const NlArgs& g, double* prev_change, hipStream_t s);
 hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s);
 hipError_t nl_finish(const int32_t* round_status, int iterations, int32_t* status, hipStream_t s);
 // dst[i] = src[i] for i < count, each side float (f32 set) or double.
-hipError_t nl_convert(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s);
+hipError_t convert_array(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s);
 
 // Finite state and control spaces (Section III-D).  The horizon is cut into
 // NC <= kFsMaxNC chunks of B steps, the chunks into groups of kFsGroup.

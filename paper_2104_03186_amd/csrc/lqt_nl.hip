@@ -131,7 +131,7 @@ hipError_t nl_change(const NlArgs& g, double* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t nl_convert(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s) {
+hipError_t convert_array(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const unsigned grid = grid_for(count);
     if (src_f32 && !dst_f32)

@@ -216,17 +216,22 @@ int chunk_length(const lqt_routing& R, int64_t T) {
 
 struct Layout {
     size_t cst, der, lane_el, wave_val, lane_aff, wave_x, mid_el, blk_val, K, d, m2_el, m2_val, m2_mid, m2_blk, S, v,
-        total;
+        x, u, total;
     int64_t NC;
     int B, NG, NB;
 };
 
 // m2: forward pass by prefixes (Method 2), which reads S and v (scratch when
-// the caller does not take them).
+// the caller does not take them).  wide: Method 2 with float results -- the
+// solve runs with double results in scratch (S, v, K, d, x, u) and they are
+// rounded to the caller's float arrays afterwards, since the states of
+// Method 2 are solved from S_k and v_k (I + C S_k is ill-conditioned enough
+// that float-rounded S_k, v_k would cost the 1e-5 accuracy of the controls).
 Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool need_d, bool m2 = false,
-                  bool need_S = false, bool need_v = false) {
+                  bool need_S = false, bool need_v = false, bool wide = false) {
     using namespace lqt;
     Layout L{};
+    if (wide) need_K = need_d = need_S = need_v = true;
     const int n = p.nx, m = p.nu;
     L.B = chunk_length(R, p.T);
     L.NC = (p.T + L.B - 1) / L.B;
@@ -256,6 +261,8 @@ Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool 
     L.m2_blk = take(m2 && blocks ? (size_t)L.NB * small_val_doubles(n) : 0);
     L.S = take(m2 && need_S ? (size_t)(p.T + 1) * n * n : 0);
     L.v = take(m2 && need_v ? (size_t)(p.T + 1) * n : 0);
+    L.x = take(m2 && wide ? (size_t)(p.T + 1) * n : 0);
+    L.u = take(m2 && wide ? (size_t)p.T * m : 0);
     L.total = off;
     return L;
 }
@@ -309,13 +316,16 @@ struct BatchSize {
     lqt_plan_t plan = nullptr;
     size_t gen = 0, small = 0, wave = 0;
     size_t nwave = 0;
-    explicit BatchSize(lqt_plan_t pl) : plan(pl) {}
+    bool f32 = false;  // float results
+    BatchSize(lqt_plan_t pl, bool f) : plan(pl), f32(f) {}
+    explicit BatchSize(lqt_plan_t pl) : plan(pl), f32(pl->desc.prec == LQT_PREC_MIXED) {}
     void add(const lqt_problem& p0, const lqt_outputs& o) {
         gen += gen_bytes(p0, o);
         const lqt_problem p = std_shape(p0);
         if (path_of(plan->route, p) == Path::Small) {
             const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && (o.x || o.u);
-            small = std::max(small, align_up(layout_for(plan->route, p, !o.K, !o.d, m2, !o.S, !o.v).total));
+            small = std::max(small,
+                             align_up(layout_for(plan->route, p, !o.K, !o.d, m2, !o.S, !o.v, m2 && f32).total));
         } else {
             wave += wave_bytes(plan, p) + wave_kd_bytes(p, o);
             ++nwave;
@@ -397,18 +407,20 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     const bool fwd = o.x || o.u;
     const bool need_K = !o.K, need_d = !o.d;
     const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && fwd;
-    Layout L = layout_for(plan->route, p, need_K, need_d, m2, !o.S, !o.v);
+    const bool wide = m2 && f32;
+    Layout L = layout_for(plan->route, p, need_K, need_d, m2, !o.S, !o.v, wide);
     lqt::SmallArgs a{};
     a.F = p.F; a.c = p.c; a.L = p.L; a.U = p.U; a.H = p.H; a.X = p.X; a.r = p.r;
     a.HT = p.HT; a.XT = p.XT; a.rT = p.rT; a.x0 = p.x0;
     a.T = p.T; a.n = p.nx; a.m = p.nu; a.p = p.ny; a.pT = p.nyT;
     a.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-    a.S = o.S ? o.S : (m2 ? (void*)(base + L.S) : nullptr);
-    a.v = o.v ? o.v : (m2 ? (void*)(base + L.v) : nullptr);
-    a.K = o.K ? o.K : (void*)(base + L.K);
-    a.d = o.d ? o.d : (void*)(base + L.d);
-    a.x = o.x; a.u = o.u;
-    a.f32 = f32 ? 1 : 0;
+    a.S = (o.S && !wide) ? o.S : (m2 ? (void*)(base + L.S) : nullptr);
+    a.v = (o.v && !wide) ? o.v : (m2 ? (void*)(base + L.v) : nullptr);
+    a.K = (o.K && !wide) ? o.K : (void*)(base + L.K);
+    a.d = (o.d && !wide) ? o.d : (void*)(base + L.d);
+    a.x = wide ? (o.x ? (void*)(base + L.x) : nullptr) : o.x;
+    a.u = wide ? (o.u ? (void*)(base + L.u) : nullptr) : o.u;
+    a.f32 = (f32 && !wide) ? 1 : 0;
     a.status = status_override ? status_override : o.status;
     a.cst = (double*)(base + L.cst);
     a.der = (double*)(base + L.der);
@@ -427,6 +439,17 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.m2_blk = (double*)(base + L.m2_blk);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr, plan->has_side ? &plan->side : nullptr);
+    if (e == hipSuccess && wide) {
+        // the double results rounded into the caller's float arrays
+        if (plan->prof.on) Profiler::begin(&plan->prof, "narrow", s);
+        const int64_t T = p.T, n = p.nx, m = p.nu;
+        const void* src[6] = {a.S, a.v, a.K, a.d, a.x, a.u};
+        void* dst[6] = {o.S, o.v, o.K, o.d, o.x, o.u};
+        const int64_t cnt[6] = {(T + 1) * n * n, (T + 1) * n, T * m * n, T * m, (T + 1) * n, T * m};
+        for (int i = 0; i < 6 && e == hipSuccess; ++i)
+            if (dst[i]) e = lqt::convert_array(src[i], false, dst[i], true, cnt[i], s);
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+    }
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return LQT_OK;
 }
@@ -449,7 +472,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     std::stable_sort(wave.begin(), wave.end(), [&](int a, int b) { return cls(a) < cls(b); });
     // workspace: [generalised-cost transforms] [small-path region (largest small instance)] [wave region]
     // [instance table]
-    BatchSize bs(plan);
+    BatchSize bs(plan, f32);
     for (int i = 0; i < count; ++i) bs.add(probs[i], outs[i]);
     std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
     size_t wave_need = 0;
@@ -1062,8 +1085,8 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
     };
     if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
     if (f32) {
-        if ((st = launched(lqt::nl_convert(x, true, xd, false, (T + 1) * n, s))) != LQT_OK) return st;
-        if ((st = launched(lqt::nl_convert(u, true, ud, false, T * m, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(x, true, xd, false, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(u, true, ud, false, T * m, s))) != LQT_OK) return st;
     }
     for (int it = 0; it < iterations; ++it) {
         // the change of round it - 1 is completed by this round's linearisation
@@ -1081,8 +1104,8 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
         if (st != LQT_OK) return st;
     }
     if (f32) {
-        if ((st = launched(lqt::nl_convert(xd, false, x, true, (T + 1) * n, s))) != LQT_OK) return st;
-        if ((st = launched(lqt::nl_convert(ud, false, u, true, T * m, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(xd, false, x, true, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(ud, false, u, true, T * m, s))) != LQT_OK) return st;
     }
     return launched(lqt::nl_finish(round_status, iterations, status, s));
 }

@@ -424,42 +424,62 @@ WDI void ttrsm_l(const double* R, double* B, int lane) {
     wsync();
 }
 
-// Ai = A^{-1} for a symmetric positive definite A (Gauss-Jordan without
-// pivoting: the pivots of an SPD matrix are positive).  Only the leading m x m
-// block is eliminated; the padded block is the identity and stays so.  A is
-// destroyed.  Returns false if a pivot is not > 0 (including NaN).
+// Lower Cholesky factor of the leading m x m block in place (upper triangle
+// zeroed); the padded block is the identity and stays so.  Returns false if a
+// pivot is not > 0 (including NaN).
 template <int N>
-WDI bool tspdinv(double* A, double* Ai, int m, int lane) {
+WDI bool tchol_m(double* A, int m, int lane) {
     constexpr int ld = TL<N>::ld;
-    for (int idx = lane; idx < N * N; idx += kW) {
-        const int r = idx / N, q = idx % N;
-        Ai[r * ld + q] = (r == q) ? 1.0 : 0.0;
-    }
-    wsync();
     bool ok = true;
 #pragma unroll 1
-    for (int k = 0; k < m; ++k) {
-        const double piv = A[k * ld + k];
-        ok = ok && (piv > 0.0);
-        const double inv = 1.0 / piv;
+    for (int j = 0; j < m; ++j) {
+        double s = A[j * ld + j];
+        for (int k = 0; k < j; ++k) s = fma(-A[j * ld + k], A[j * ld + k], s);
+        ok = ok && (s > 0.0);
+        const double rjj = sqrt(s);
+        const double rinv = 1.0 / rjj;
         wsync();
-        if (lane < m) {
-            A[k * ld + lane] *= inv;
-            Ai[k * ld + lane] *= inv;
+        if (lane == j) A[j * ld + j] = rjj;
+        if (lane > j && lane < m) {
+            double t = A[lane * ld + j];
+            for (int k = 0; k < j; ++k) t = fma(-A[lane * ld + k], A[j * ld + k], t);
+            A[lane * ld + j] = t * rinv;
         }
-        wsync();
-        for (int idx = lane; idx < m * m; idx += kW) {
-            const int r = idx / m, q = idx - (idx / m) * m;
-            if (r == k) continue;
-            const double fr = A[r * ld + k];
-            Ai[r * ld + q] = fma(-fr, Ai[k * ld + q], Ai[r * ld + q]);
-            if (q != k) A[r * ld + q] = fma(-fr, A[k * ld + q], A[r * ld + q]);
-        }
-        wsync();
-        if (lane < m && lane != k) A[lane * ld + k] = 0.0;
+        if (lane < j) A[lane * ld + j] = 0.0;
         wsync();
     }
     return ok;
+}
+
+// Triangular solves with the factor R of tchol_m (rows and columns >= m are
+// the identity): B <- R^{-1} B (forward) or B <- R^{-T} B (backward) for the
+// N columns of B, lane c solving column c, and, when x is given, the vector x
+// solved the same way by lane N (a wavefront has 64 lanes, N <= 32).
+template <int N, bool TRANS>
+WDI void ttrsm_m(const double* R, double* B, double* x, int m, int lane) {
+    constexpr int ld = TL<N>::ld;
+    if (lane < N || (x && lane == N)) {
+        double* col = lane < N ? B + lane : x;
+        const int cs = lane < N ? ld : 1;
+        if (!TRANS) {
+#pragma unroll 1
+            for (int i = 0; i < m; ++i) {
+                double s = col[i * cs];
+#pragma unroll 4
+                for (int k = 0; k < i; ++k) s = fma(-R[i * ld + k], col[k * cs], s);
+                col[i * cs] = s / R[i * ld + i];
+            }
+        } else {
+#pragma unroll 1
+            for (int i = m - 1; i >= 0; --i) {
+                double s = col[i * cs];
+#pragma unroll 4
+                for (int k = i + 1; k < m; ++k) s = fma(-R[k * ld + i], col[k * cs], s);
+                col[i * cs] = s / R[i * ld + i];
+            }
+        }
+    }
+    wsync();
 }
 
 // Mi = M^{-1}, Gauss-Jordan with partial pivoting (M destroyed).
@@ -614,43 +634,43 @@ WDI void tvec_load(int n, const double* g, double* l, int lane) {
 }
 
 // P <- a_k (x) P, matrix inversion lemma form of the combination rule with
-// C_k = G G^T: W = I + G^T J_P G (m x m SPD) and, with Z = G^T J_P,
+// C_k = G G^T: W = I + G^T J_P G = R R^T (m x m, W >= I), Z = G^T J_P,
+// V = R^{-1} Z, Q = (A_P G) R^{-T}, y = R^{-1} (G^T eta_P - Z c); then
 //   (I + C_k J_P)^{-1} = I - G W^{-1} Z,
-//   A' = A_P F - (A_P G) W^{-1} Z F,   C' = C_P + (A_P G) W^{-1} (A_P G)^T,
-//   b' = A_P (c + G h) + b_P,          eta' = F^T (eta_P - J_P c - Z^T h) + eta_k,
-//   J' = F^T (J_P - Z^T W^{-1} Z) F + J_k,   h = W^{-1} (G^T eta_P - Z c).
+//   A' = A_P F - Q (V F),        C' = C_P + Q Q^T,
+//   b' = A_P c + Q y + b_P,      eta' = F^T (eta_P - J_P c - V^T y) + eta_k,
+//   J' = F^T (J_P - V^T V) F + J_k.
+// Every inverse is applied as triangular solves with the Cholesky factor, and
+// the symmetric updates are products of a factor with itself.
 template <int N>
 WDI void t_step_combine(int m, const double* F, const double* c, const double* G, const double* ek,
                         const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, TSlots<N>& s,
                         int lane) {
-    constexpr int ld = TL<N>::ld;
     double* Z = s.m[7];
-    double* Wm = s.m[8];
-    double* Wi = s.m[9];
-    double* AG = s.m[10];
+    double* Rf = s.m[8];
+    double* VF = s.m[9];
+    double* Qt = s.m[10];
     double* T9 = s.m[11];
-    double* X1 = s.m[12];
-    double *h = s.v[5], *hw = s.v[6], *w = s.v[7], *nb = s.v[8], *ne = s.v[9];
+    double *y = s.v[5], *w = s.v[7], *nb = s.v[8], *ne = s.v[9];
+    constexpr int ld = TL<N>::ld;
     tgemm<N, true, false>(G, PJ, Z, 1.0, 0.0, lane);               // Z = G^T J_P
-    tgemm<N, false, false, true>(Z, G, Wm, 1.0, 0.0, lane);        // Z G
-    if (lane < N) Wm[lane * ld + lane] += 1.0;
+    tgemm<N, false, false, true>(Z, G, Rf, 1.0, 0.0, lane);        // Z G
+    if (lane < N) Rf[lane * ld + lane] += 1.0;
     wsync();
-    tspdinv<N>(Wm, Wi, m, lane);                                   // W >= I: always SPD
-    tgemm<N, false, false>(Wi, Z, X1, 1.0, 0.0, lane);             // W^{-1} Z
-    tgemm<N, false, false>(PA, G, AG, 1.0, 0.0, lane);             // A_P G
-    // h = W^{-1} (G^T eta_P - Z c)
-    tgemv<N, true>(G, Pe, h, 1.0, 0.0, lane);
-    tgemv<N, false>(Z, c, h, -1.0, 1.0, lane);
-    tgemv<N, false>(Wi, h, hw, 1.0, 0.0, lane);
-    // b' = A_P (c + G h) + b_P
-    tgemv<N, false>(G, hw, w, 1.0, 0.0, lane);
-    if (lane < N) w[lane] += c[lane];
-    wsync();
-    tgemv<N, false>(PA, w, nb, 1.0, 0.0, lane);
-    // eta' = F^T (eta_P - J_P c - Z^T h) + eta_k
+    tchol_m<N>(Rf, m, lane);                                       // W >= I: always SPD
+    // y0 = G^T eta_P - Z c, then V = R^{-1} Z (in Z) and y = R^{-1} y0
+    tgemv<N, true>(G, Pe, y, 1.0, 0.0, lane);
+    tgemv<N, false>(Z, c, y, -1.0, 1.0, lane);
+    ttrsm_m<N, false>(Rf, Z, y, m, lane);
+    tgemm<N, true, true>(G, PA, Qt, 1.0, 0.0, lane);               // (A_P G)^T
+    ttrsm_m<N, false>(Rf, Qt, nullptr, m, lane);                   // Q^T = R^{-1} (A_P G)^T
+    // b' = A_P c + Q y + b_P
+    tgemv<N, false>(PA, c, nb, 1.0, 0.0, lane);
+    tgemv<N, true>(Qt, y, nb, 1.0, 1.0, lane);
+    // eta' = F^T (eta_P - J_P c - V^T y) + eta_k
     tgemv<N, false>(PJ, c, w, -1.0, 0.0, lane);
-    tgemv<N, true>(Z, hw, h, 1.0, 0.0, lane);
-    if (lane < N) w[lane] += Pe[lane] - h[lane];
+    tgemv<N, true>(Z, y, w, -1.0, 1.0, lane);
+    if (lane < N) w[lane] += Pe[lane];
     wsync();
     tgemv<N, true>(F, w, ne, 1.0, 0.0, lane);
     if (lane < N) {
@@ -658,16 +678,15 @@ WDI void t_step_combine(int m, const double* F, const double* c, const double* G
         Pe[lane] = ne[lane] + ek[lane];
     }
     wsync();
-    // C' = C_P + (A_P G) W^{-1} (A_P G)^T
-    tgemm<N, false, false>(AG, Wi, T9, 1.0, 0.0, lane);
-    tgemm<N, false, true, true>(T9, AG, PC, 1.0, 1.0, lane);
-    // A' = A_P F - (A_P G)(W^{-1} Z F)
-    tgemm<N, false, false>(X1, F, Wm, 1.0, 0.0, lane);
+    // C' = C_P + Q Q^T
+    tgemm<N, true, false, true>(Qt, Qt, PC, 1.0, 1.0, lane);
+    // A' = A_P F - Q (V F)
+    tgemm<N, false, false>(Z, F, VF, 1.0, 0.0, lane);
     tgemm<N, false, false>(PA, F, T9, 1.0, 0.0, lane);
-    tgemm<N, false, false>(AG, Wm, T9, -1.0, 1.0, lane);
+    tgemm<N, true, false>(Qt, VF, T9, -1.0, 1.0, lane);
     tcopy<N>(T9, PA, lane);
-    // J' = F^T (J_P - Z^T W^{-1} Z) F + J_k
-    tgemm<N, true, false, true>(Z, X1, PJ, -1.0, 1.0, lane);
+    // J' = F^T (J_P - V^T V) F + J_k
+    tgemm<N, true, false, true>(Z, Z, PJ, -1.0, 1.0, lane);
     tgemm<N, false, false>(PJ, F, T9, 1.0, 0.0, lane);
     tgemm<N, true, false, true>(F, T9, PJ, 1.0, 0.0, lane);
     for (int idx = lane; idx < N * N; idx += kW) PJ[(idx / N) * ld + idx % N] += Js[(idx / N) * ld + idx % N];
@@ -810,7 +829,7 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
     const uint32_t ps = I.per_step;
     const bool var = (ps & (kPS_L | kPS_U | kPS_H | kPS_X)) != 0;
     double *Sm = s.m[0], *F = s.m[1], *L = s.m[2], *Um = s.m[3], *Js = s.m[4], *W = s.m[5];
-    double *SL = s.m[6], *R = s.m[7], *SF = s.m[8], *Y = s.m[9], *K = s.m[10];
+    double *SL = s.m[6], *R = s.m[7], *SF = s.m[8], *K = s.m[10];
     double *Phi = s.m[11], *Ft = s.m[12], *T13 = s.m[13];
     double *v = s.v[0], *cc = s.v[1], *ek = s.v[2], *w = s.v[3], *z = s.v[4], *d = s.v[5];
     double *phi = s.v[6], *ct = s.v[7], *nv = s.v[8], *t9 = s.v[9], *rk = s.v[10];
@@ -851,7 +870,7 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
             wsync();
             teta<N>(W, rk, p, ek, lane);
         }
-        // M_k = L^T S L + U, inverted (SPD)
+        // M_k = L^T S L + U = R R^T (Cholesky; SPD)
         tgemm<N, false, false>(Sm, L, SL, 1.0, 0.0, lane);
         for (int idx = lane; idx < N * N; idx += kW) {  // symmetrised U (identity on the padding)
             const int a = idx / N, b = idx % N;
@@ -859,22 +878,25 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
         }
         wsync();
         tgemm<N, true, false, true>(L, SL, R, 1.0, 1.0, lane);
-        ok = tspdinv<N>(R, Y, m, lane) && ok;                      // Y := M_k^{-1}
-        // K = M^{-1} L^T S F ; P = L^T S F in SL
+        ok = tchol_m<N>(R, m, lane) && ok;
+        // P = L^T S F, then V = R^{-1} P (in SL) and K = R^{-T} V
         tgemm<N, false, false>(Sm, F, SF, 1.0, 0.0, lane);
         tgemm<N, true, false>(L, SF, SL, 1.0, 0.0, lane);
-        tgemm<N, false, false>(Y, SL, K, 1.0, 0.0, lane);
-        // w = v - S c ; z = L^T w ; d = M^{-1} z
+        // w = v - S c ; z = L^T w ; zr = R^{-1} z (in z) ; d = R^{-T} zr
         tgemv<N, false>(Sm, cc, w, -1.0, 0.0, lane);
         if (lane < N) w[lane] += v[lane];
         wsync();
         tgemv<N, true>(L, w, z, 1.0, 0.0, lane);
-        tgemv<N, false>(Y, z, d, 1.0, 0.0, lane);
-        // S' = F^T S F - P^T K + J ; v' = F^T w - K^T z + eta
+        ttrsm_m<N, false>(R, SL, z, m, lane);
+        tcopy<N>(SL, K, lane);
+        if (lane < N) d[lane] = z[lane];
+        wsync();
+        ttrsm_m<N, true>(R, K, d, m, lane);
+        // S' = F^T S F - V^T V + J ; v' = F^T w - V^T zr + eta
         tgemm<N, true, false, true>(F, SF, T13, 1.0, 0.0, lane);
-        tgemm<N, true, false, true>(SL, K, T13, -1.0, 1.0, lane);
+        tgemm<N, true, false, true>(SL, SL, T13, -1.0, 1.0, lane);
         tgemv<N, true>(F, w, nv, 1.0, 0.0, lane);
-        tgemv<N, true>(K, z, nv, -1.0, 1.0, lane);
+        tgemv<N, true>(SL, z, nv, -1.0, 1.0, lane);
         for (int idx = lane; idx < N * N; idx += kW)
             Sm[(idx / N) * ld + idx % N] = T13[(idx / N) * ld + idx % N] + Js[(idx / N) * ld + idx % N];
         if (lane < N) v[lane] = nv[lane] + ek[lane];
