@@ -175,6 +175,25 @@ lqt_status lqt_plan(const lqt_plan_desc *desc, lqt_plan_t *out);
 lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
                      int32_t count, void *stream);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Solves one instance like lqt_solve (same routing, kernels and
+ * results, bit for bit, as lqt_solve on the same plan), stream-ordered and
+ * asynchronous, but keeps the whole workspace in a fixed 64 MiB device array
+ * of the library instead of plan memory: it calls no hipMalloc, hipFree or
+ * other allocating routine (and records no timing events).  The array exists
+ * once per device, is held until the process ends, and is shared by every
+ * lqt_solve_noalloc call on that device, whatever the plan: calls whose work
+ * overlaps on one device (different streams, or host threads with different
+ * plans) race on it and must be ordered by the caller.  The solve writes every
+ * workspace value before reading it, so nothing needs clearing between calls.
+ * Limits: the instance's workspace must fit 64 MiB (LQT_ENOMEM otherwise,
+ * nothing enqueued); e.g. an nx = 4, nu = 2 instance of T = 10^6 that passes K
+ * and d needs about 33 MB.  Argument errors as lqt_solve (LQT_EINVAL,
+ * LQT_ENOTSUP); LQT_EHIP if the array's device address could not be read when
+ * the plan was created. */
+lqt_status lqt_solve_noalloc(lqt_plan_t plan, const lqt_problem *prob, const lqt_outputs *out, void *stream);
+
 /* Autotuner.  Times the given instances (solved into outs, stream-ordered on
  * `stream`, synchronous) with several chunk lengths for every launch group
  * (size class 8, 16, 32, 64 x wavefront / workgroup engine) present, and

@@ -22,7 +22,7 @@ PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
             "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate",
-            "lqt_fs_solve", "lqt_set_routing")
+            "lqt_fs_solve", "lqt_set_routing", "lqt_solve_noalloc")
 
 _vp = ctypes.c_void_p
 
@@ -103,6 +103,8 @@ def load() -> ctypes.CDLL:
     lib.lqt_plan.restype = ctypes.c_int
     lib.lqt_solve.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.c_int32, _vp]
     lib.lqt_solve.restype = ctypes.c_int
+    lib.lqt_solve_noalloc.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), _vp]
+    lib.lqt_solve_noalloc.restype = ctypes.c_int
     lib.lqt_tune.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(Outputs), ctypes.c_int32, _vp,
                              ctypes.POINTER(ctypes.c_int32)]
     lib.lqt_tune.restype = ctypes.c_int

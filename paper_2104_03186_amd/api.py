@@ -169,6 +169,16 @@ class Plan:
         sp = ctypes.c_void_p(stream.cuda_stream)
         _lib.check(_lib.load().lqt_solve(self._h, P, O, n, sp), self._h)
 
+    def solve_noalloc(self, prob: DeviceProblem, out: DeviceOutputs, stream=None) -> None:
+        """One instance through lqt_solve_noalloc: the library's fixed device
+        workspace, no allocation.  Asynchronous."""
+        self._check_dtype(out)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        ps, os_ = prob.struct(), out.struct()
+        _lib.check(_lib.load().lqt_solve_noalloc(self._h, ctypes.byref(ps), ctypes.byref(os_),
+                                                 ctypes.c_void_p(stream.cuda_stream)), self._h)
+
     def tune(self, probs: Sequence[DeviceProblem], outs: Sequence[DeviceOutputs], stream=None) -> List[int]:
         """Pick the chunk length of every launch group present from timed
         solves of these instances (lqt_tune); returns the 8 chosen divisors."""

@@ -403,7 +403,7 @@ lqt_status ensure_ws(lqt_plan_t plan, Arena& A, size_t bytes) {
 }
 
 lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const lqt_outputs& o, hipStream_t s,
-                      int32_t* status_override, bool f32) {
+                      int32_t* status_override, bool f32, bool hooks = true) {
     const bool fwd = o.x || o.u;
     const bool need_K = !o.K, need_d = !o.d;
     const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && fwd;
@@ -437,21 +437,74 @@ lqt_status launch_one(lqt_plan_t plan, char* base, const lqt_problem& p, const l
     a.m2_val = (double*)(base + L.m2_val);
     a.m2_mid = (double*)(base + L.m2_mid);
     a.m2_blk = (double*)(base + L.m2_blk);
+    const bool prof = hooks && plan->prof.on;
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
-    hipError_t e = lqt::small_solve(a, s, plan->prof.on ? &hook : nullptr, plan->has_side ? &plan->side : nullptr);
+    hipError_t e = lqt::small_solve(a, s, prof ? &hook : nullptr, plan->has_side ? &plan->side : nullptr);
     if (e == hipSuccess && wide) {
         // the double results rounded into the caller's float arrays
-        if (plan->prof.on) Profiler::begin(&plan->prof, "narrow", s);
+        if (prof) Profiler::begin(&plan->prof, "narrow", s);
         const int64_t T = p.T, n = p.nx, m = p.nu;
         const void* src[6] = {a.S, a.v, a.K, a.d, a.x, a.u};
         void* dst[6] = {o.S, o.v, o.K, o.d, o.x, o.u};
         const int64_t cnt[6] = {(T + 1) * n * n, (T + 1) * n, T * m * n, T * m, (T + 1) * n, T * m};
         for (int i = 0; i < 6 && e == hipSuccess; ++i)
             if (dst[i]) e = lqt::convert_array(src[i], false, dst[i], true, cnt[i], s);
-        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        if (prof) Profiler::end(&plan->prof, s);
     }
     if (e != hipSuccess) return fail(plan, LQT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return LQT_OK;
+}
+
+// Generalised instance (Section IV-D): lay out its transform at `ws` (taking
+// `off` bytes forward), enqueue the transform to the standard form and turn
+// (tp, to) -- copies of the instance and its outputs -- into the standard-form
+// instance the solve takes.  g keeps what the map-back needs.
+lqt_status gen_prepare(lqt_plan_t plan, char* ws, size_t& off, const lqt_problem& p, const lqt_outputs& o,
+                       lqt_problem& tp, lqt_outputs& to, bool f32, hipStream_t s, lqt::GenArgs& g) {
+    g = lqt::GenArgs{};
+    g.F = p.F; g.c = p.c; g.L = p.L; g.H = p.H; g.X = p.X; g.U = p.U; g.M = p.M; g.r = p.r; g.s = p.s;
+    g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny;
+    g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+    lqt::gen_layout(g, (double*)(ws + off));
+    off += align_up(lqt::gen_ws_doubles(p.nx, p.nu, p.ny, p.T, p.per_step & LQT_PS_F) * sizeof(double));
+    tp = p;
+    to = o;
+    if (o.u && !o.x) {
+        to.x = ws + off;
+        off += align_up((size_t)(p.T + 1) * p.nx * sizeof(double));
+    }
+    g.K = to.K; g.d = to.d; g.u = to.u; g.x = to.x;
+    g.f32 = f32 ? 1 : 0;
+    tp.F = g.Ft; tp.c = g.ct; tp.X = g.Xt;
+    tp.per_step |= LQT_PS_c;
+    tp.M = nullptr;
+    tp.s = nullptr;
+    hipError_t e = lqt::gen_transform(g, s);
+    if (e != hipSuccess) return fail(plan, LQT_EHIP, "transform launch failed: %s", hipGetErrorString(e));
+    return LQT_OK;
+}
+
+// Instance-table entry of a chunked-path instance whose workspace starts at
+// ws and whose K, d scratch (used when the caller does not take K and d)
+// starts at kd.
+lqt::GInst make_ginst(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, char* ws, char* kd,
+                      int64_t chunk0, int32_t* status) {
+    lqt::GInst g{};
+    g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
+    g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
+    g.S = o.S; g.v = o.v; g.x = o.x; g.u = o.u;
+    double* kdd = (double*)kd;  // sized for double gains; float ones use part of it
+    g.K = o.K ? o.K : (void*)kdd;
+    g.d = o.d ? o.d : (void*)(kdd + (size_t)p.T * p.nu * p.nx);
+    g.status = status;
+    g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
+    g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+    g.B = chunk_for(plan, p);
+    g.NC = (p.T + g.B - 1) / g.B;
+    g.chunk0 = chunk0;
+    g.ws = (double*)ws;
+    g.eng = eng_of(plan->route, p);
+    return g;
 }
 
 // Solve a set of instances on stream s in arena A.  status_override (if not
@@ -495,26 +548,10 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         size_t off = 0;
         if (plan->prof.on) Profiler::begin(&plan->prof, "gen_transform", s);
         for (int i = 0; i < count; ++i) {
-            const lqt_problem& p = probs[i];
-            if (!is_gen(p)) continue;
-            lqt::GenArgs g{};
-            g.F = p.F; g.c = p.c; g.L = p.L; g.H = p.H; g.X = p.X; g.U = p.U; g.M = p.M; g.r = p.r; g.s = p.s;
-            g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny;
-            g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-            lqt::gen_layout(g, (double*)(A.ws + off));
-            off += align_up(lqt::gen_ws_doubles(p.nx, p.nu, p.ny, p.T, p.per_step & LQT_PS_F) * sizeof(double));
-            if (outs[i].u && !outs[i].x) {
-                to[i].x = A.ws + off;
-                off += align_up((size_t)(p.T + 1) * p.nx * sizeof(double));
-            }
-            g.K = to[i].K; g.d = to[i].d; g.u = to[i].u; g.x = to[i].x;
-            g.f32 = f32 ? 1 : 0;
-            tp[i].F = g.Ft; tp[i].c = g.ct; tp[i].X = g.Xt;
-            tp[i].per_step |= LQT_PS_c;
-            tp[i].M = nullptr;
-            tp[i].s = nullptr;
-            hipError_t e = lqt::gen_transform(g, s);
-            if (e != hipSuccess) return fail(plan, LQT_EHIP, "transform launch failed: %s", hipGetErrorString(e));
+            if (!is_gen(probs[i])) continue;
+            lqt::GenArgs g;
+            st = gen_prepare(plan, A.ws, off, probs[i], outs[i], tp[i], to[i], f32, s, g);
+            if (st != LQT_OK) return st;
             gens.push_back(g);
         }
         if (plan->prof.on) Profiler::end(&plan->prof, s);
@@ -557,22 +594,9 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         const lqt_problem& p = probs[wave[j]];
         const lqt_outputs& o = outs[wave[j]];
         lqt::GInst& g = A.ginst_host[j];
-        g = lqt::GInst{};
-        g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
-        g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
-        g.S = o.S; g.v = o.v; g.x = o.x; g.u = o.u;
-        double* kd = (double*)(wbase + kd_off[j]);  // sized for FP64 gains; FP32 ones use part of it
-        g.K = o.K ? o.K : (void*)kd;
-        g.d = o.d ? o.d : (void*)(kd + (size_t)p.T * p.nu * p.nx);
-        g.status = status_override ? status_override[wave[j]] : o.status;
-        g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
-        g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
-        g.B = chunk_for(plan, p);
-        g.NC = (p.T + g.B - 1) / g.B;
-        g.chunk0 = chunk0;
+        g = make_ginst(plan, p, o, wbase + ws_off[j], wbase + kd_off[j], chunk0,
+                       status_override ? status_override[wave[j]] : o.status);
         chunk0 += g.NC;
-        g.ws = (double*)(wbase + ws_off[j]);
-        g.eng = eng_of(plan->route, p);
         want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
     }
     lqt::GInst* d_inst = (lqt::GInst*)(wbase + bs.wave);
@@ -603,6 +627,96 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         j0 = j1;
     }
     return post();
+}
+
+// ---- allocation-free solve ---------------------------------------------------
+//
+// lqt_solve_noalloc keeps its workspace in `scratch`, a fixed device array of
+// the library (one per device, held until the process ends), instead of
+// memory the plan allocates.  Host code reaches it only through the device
+// address read once per device at plan creation (noalloc_base).
+
+}  // namespace
+
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+// Reads this device's address of `scratch` (the device must be current).
+// Once per device; a failure leaves the pointer null and lqt_solve_noalloc
+// then reports LQT_EHIP.
+void noalloc_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[dev]) return;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    g_noalloc_ptr[dev] = (char*)ptr;
+}
+
+char* noalloc_base(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc_ptr[dev];
+}
+
+// Stores one instance-table entry into device memory from the kernel's
+// arguments (no host staging buffer).
+__global__ void k_put_inst(lqt::GInst g, lqt::GInst* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = g;
+}
+
+// One instance solved with its whole workspace in [base, base + cap): the
+// regions of solve_all for a batch of one, the instance table included.
+// Enqueues kernels only: no device or host allocation, no events.
+lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_problem& p0, const lqt_outputs& o0,
+                        hipStream_t s) {
+    const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
+    BatchSize bs(plan, f32);
+    bs.add(p0, o0);
+    if (bs.total() > cap)
+        return fail(plan, LQT_ENOMEM,
+                    "lqt_solve_noalloc: the instance needs %zu bytes of workspace, the static workspace holds %zu "
+                    "(nx=%d nu=%d T=%lld)", bs.total(), cap, p0.nx, p0.nu, (long long)p0.T);
+    lqt_problem p = p0;
+    lqt_outputs o = o0;
+    lqt::GenArgs g{};
+    const bool gen = is_gen(p0);
+    lqt_status st = LQT_OK;
+    if (gen) {
+        size_t off = 0;
+        if ((st = gen_prepare(plan, base, off, p0, o0, p, o, f32, s, g)) != LQT_OK) return st;
+    }
+    char* const b = base + bs.gen;
+    if (path_of(plan->route, p) == Path::Small) {
+        if ((st = launch_one(plan, b, p, o, s, nullptr, f32, false)) != LQT_OK) return st;
+    } else {
+        char* const ws = b + bs.small;
+        char* const kd = ws + wave_bytes(plan, std_shape(p0));
+        const lqt::GInst gi = make_ginst(plan, p, o, ws, kd, 0, o.status);
+        lqt::GInst* d_inst = (lqt::GInst*)(ws + bs.wave);
+        k_put_inst<<<1, 64, 0, s>>>(gi, d_inst);
+        hipError_t e = hipGetLastError();
+        const bool fwd = o.x || o.u;
+        const int eng = eng_of(plan->route, p);
+        if (e == hipSuccess)
+            e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr)
+                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, fwd, f32, s, nullptr);
+        if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
+    }
+    if (gen) {
+        hipError_t e = lqt::gen_post(g, s);
+        if (e != hipSuccess) return fail(plan, LQT_EHIP, "map-back launch failed: %s", hipGetErrorString(e));
+    }
+    return LQT_OK;
 }
 
 void arena_release(Arena& A) {
@@ -829,7 +943,9 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
     lqt_plan_s* p = new (std::nothrow) lqt_plan_s();
     if (!p) return fail(nullptr, LQT_ENOMEM, "lqt_plan: out of host memory");
     p->desc = *desc;
+    p->err.reserve(600);  // error texts (<= 512 bytes) are then formatted without allocating
     if (p->desc.max_inflight <= 0) p->desc.max_inflight = kDefaultQueue;
+    noalloc_init(desc->device);
     if (desc->trajectory == LQT_TRAJ_PREFIX) {
         // a failure leaves the element scan on the solve's own stream
         lqt::SideStream& sd = p->side;
@@ -900,6 +1016,21 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
     if (count == 0) return LQT_OK;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
     return solve_all(plan, plan->main, probs, outs, count, (hipStream_t)stream, nullptr);
+}
+
+lqt_status lqt_solve_noalloc(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, void* stream) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_solve_noalloc: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (!prob || !out) return fail(plan, LQT_EINVAL, "lqt_solve_noalloc: NULL problem or outputs");
+    lqt_status st = validate(plan, *prob, *out, 0);
+    if (st != LQT_OK) return st;
+    char* const base = noalloc_base(plan->desc.device);
+    if (!base)
+        return fail(plan, LQT_EHIP, "lqt_solve_noalloc: the static workspace of device %d is not available",
+                    plan->desc.device);
+    if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    return solve_static(plan, base, kNoAllocBytes, *prob, *out, (hipStream_t)stream);
 }
 
 lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs* outs, int32_t count, void* stream,
