@@ -88,10 +88,14 @@ typedef enum {
  * C_{0,k} v_k) and u_k = -K_k x_k + d_k.  The element scan does not depend
  * on the backward pass and runs on a second stream owned by the plan,
  * concurrently with it (joined before the forward walk, so the solve stays
- * ordered on the caller's stream).  LQT_TRAJ_PREFIX is provided on the lane pipeline
- * (nx <= 4, nu <= nx, T >= 8192); other instances that ask for x or u then
- * fail with LQT_ENOTSUP.  It reads S and v, held in library workspace when
- * the caller does not take them. */
+ * ordered on the caller's stream) on the lane pipeline (nx <= 4).  On the
+ * chunked engines the forward prefixes at the chunk starts come from the
+ * chunk elements of the backward pass (one combination per chunk, after the
+ * steps of the first chunk), then every chunk walks its steps.  It reads S
+ * and v, held in library workspace when the caller does not take them; with
+ * LQT_PREC_MIXED the instances are solved with double results in workspace
+ * and rounded to float afterwards (x_k is solved from S_k and v_k, which
+ * float rounding would make too inaccurate for the 1e-5 bound). */
 typedef enum {
     LQT_TRAJ_MAPS = 0,
     LQT_TRAJ_PREFIX = 1

@@ -65,6 +65,8 @@ struct GInst {
     int64_t chunk0;   // flat index of the first chunk over the launch
     double* ws;       // instance workspace (ws_doubles)
     int32_t eng;      // 0: wavefront engine; else padded dimension of the workgroup engine
+    int32_t traj;     // 1: trajectory by forward prefixes (Method 2) into m2x, m2u (x, u are then null)
+    void *m2x, *m2u;  // Method 2 states and controls (double)
 };
 
 size_t wave_lds_bytes(int nmax);
@@ -79,6 +81,10 @@ hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bo
 // n, p, pT <= 64 and m <= 32).
 hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
                        bool f32, hipStream_t s, const StageHook* h);
+// Trajectory by forward prefixes (Method 2) for the instances of a launch
+// group with traj set, after the group's backward pass (double S, v, K, d;
+// writes m2x, m2u); N = the group's size class (8, 16, 32, 64).
+hipError_t m2_chunked(int N, const GInst* d_inst, int ninst, int64_t nchunks, hipStream_t s, const StageHook* h);
 
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);

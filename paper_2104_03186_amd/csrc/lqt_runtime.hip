@@ -279,8 +279,30 @@ size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
     const int64_t wd = lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(plan->route, p), NC, B, p.c != nullptr);
     return align_up((size_t)wd * sizeof(double));
 }
-size_t wave_kd_bytes(const lqt_problem& p, const lqt_outputs& o) {
-    return (!o.K || !o.d) ? align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double)) : 0;
+// Scratch of one chunked-path instance beside its engine workspace: the
+// double gains when the caller does not take K and d, and for the forward-
+// prefix trajectory (Method 2) the double S, v it reads.  A plan with float
+// results and forward prefixes solves its chunked instances with double
+// results ("wide"): every requested family goes to double scratch first and
+// is rounded into the caller's arrays afterwards.
+struct WaveScratch {
+    bool m2 = false, wide = false;
+    size_t kd = 0, S = 0, v = 0, x = 0, u = 0;
+    size_t total() const { return kd + S + v + x + u; }
+};
+
+WaveScratch wave_scratch(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, bool f32) {
+    WaveScratch w;
+    const bool prefix = plan->desc.trajectory == LQT_TRAJ_PREFIX;
+    w.m2 = prefix && (o.x || o.u);
+    w.wide = prefix && f32;
+    const size_t T = (size_t)p.T, n = (size_t)p.nx, m = (size_t)p.nu;
+    if (!o.K || !o.d || w.wide) w.kd = align_up(T * (m * n + m) * sizeof(double));
+    if ((w.m2 && !o.S) || (w.wide && o.S) || (w.m2 && w.wide)) w.S = align_up((T + 1) * n * n * sizeof(double));
+    if ((w.m2 && !o.v) || (w.wide && o.v) || (w.m2 && w.wide)) w.v = align_up((T + 1) * n * sizeof(double));
+    if (w.m2 && w.wide && o.x) w.x = align_up((T + 1) * n * sizeof(double));
+    if (w.m2 && w.wide && o.u) w.u = align_up(T * m * sizeof(double));
+    return w;
 }
 
 // Generalised stage cost (Section IV-D): an instance with M or s is solved as
@@ -327,7 +349,7 @@ struct BatchSize {
             small = std::max(small,
                              align_up(layout_for(plan->route, p, !o.K, !o.d, m2, !o.S, !o.v, m2 && f32).total));
         } else {
-            wave += wave_bytes(plan, p) + wave_kd_bytes(p, o);
+            wave += wave_bytes(plan, p) + wave_scratch(plan, p0, o, f32).total();
             ++nwave;
         }
     }
@@ -342,10 +364,6 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
-    if (plan->desc.trajectory == LQT_TRAJ_PREFIX && path_of(plan->route, p) != Path::Small && (o.x || o.u))
-        return fail(plan, LQT_ENOTSUP,
-                    "instance %d: the forward-prefix trajectory is provided on the n <= 4 lane pipeline only "
-                    "(nx=%d nu=%d T=%lld)", idx, p.nx, p.nu, (long long)p.T);
     if (path_of(plan->route, p) == Path::Wave) {
         if (std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
             return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
@@ -488,14 +506,25 @@ lqt_status gen_prepare(lqt_plan_t plan, char* ws, size_t& off, const lqt_problem
 // ws and whose K, d scratch (used when the caller does not take K and d)
 // starts at kd.
 lqt::GInst make_ginst(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, char* ws, char* kd,
-                      int64_t chunk0, int32_t* status) {
+                      int64_t chunk0, int32_t* status, const WaveScratch& w) {
     lqt::GInst g{};
     g.F = p.F; g.c = p.c; g.L = p.L; g.U = p.U; g.H = p.H; g.X = p.X; g.r = p.r;
     g.HT = p.HT; g.XT = p.XT; g.rT = p.rT; g.x0 = p.x0;
     g.S = o.S; g.v = o.v; g.x = o.x; g.u = o.u;
     double* kdd = (double*)kd;  // sized for double gains; float ones use part of it
-    g.K = o.K ? o.K : (void*)kdd;
-    g.d = o.d ? o.d : (void*)(kdd + (size_t)p.T * p.nu * p.nx);
+    g.K = (o.K && !w.wide) ? o.K : (void*)kdd;
+    g.d = (o.d && !w.wide) ? o.d : (void*)(kdd + (size_t)p.T * p.nu * p.nx);
+    char* sc = kd + w.kd;  // Method 2 / wide scratch: S | v | x | u
+    if (w.S) g.S = sc;
+    if (w.v) g.v = sc + w.S;
+    if (w.wide && !w.S) g.S = nullptr;
+    if (w.wide && !w.v) g.v = nullptr;
+    if (w.m2) {
+        g.traj = 1;
+        g.x = g.u = nullptr;
+        g.m2x = w.wide ? (o.x ? (void*)(sc + w.S + w.v) : nullptr) : o.x;
+        g.m2u = w.wide ? (o.u ? (void*)(sc + w.S + w.v + w.x) : nullptr) : o.u;
+    }
     g.status = status;
     g.T = p.T; g.n = p.nx; g.m = p.nu; g.p = p.ny; g.pT = p.nyT;
     g.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
@@ -528,12 +557,14 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     BatchSize bs(plan, f32);
     for (int i = 0; i < count; ++i) bs.add(probs[i], outs[i]);
     std::vector<int64_t> ws_off(wave.size()), kd_off(wave.size());
+    std::vector<WaveScratch> wsc(wave.size());
     size_t wave_need = 0;
     for (size_t j = 0; j < wave.size(); ++j) {
         ws_off[j] = (int64_t)wave_need;
         wave_need += wave_bytes(plan, std_shape(probs[wave[j]]));
         kd_off[j] = (int64_t)wave_need;
-        wave_need += wave_kd_bytes(probs[wave[j]], outs[wave[j]]);
+        wsc[j] = wave_scratch(plan, probs[wave[j]], outs[wave[j]], f32);
+        wave_need += wsc[j].total();
     }
     lqt_status st = ensure_ws(plan, A, bs.total());
     if (st != LQT_OK) return st;
@@ -595,9 +626,9 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         const lqt_outputs& o = outs[wave[j]];
         lqt::GInst& g = A.ginst_host[j];
         g = make_ginst(plan, p, o, wbase + ws_off[j], wbase + kd_off[j], chunk0,
-                       status_override ? status_override[wave[j]] : o.status);
+                       status_override ? status_override[wave[j]] : o.status, wsc[j]);
         chunk0 += g.NC;
-        want_fwd_c[j] = (o.x || o.u) ? 1 : 0;
+        want_fwd_c[j] = (g.x || g.u) ? 1 : (g.traj ? 2 : 0);
     }
     lqt::GInst* d_inst = (lqt::GInst*)(wbase + bs.wave);
     if (hipMemcpyAsync(d_inst, A.ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
@@ -607,24 +638,52 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         return fail(plan, LQT_EHIP, "event creation failed");
     (void)hipEventRecord(A.ginst_done, s);
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
+    // chunked groups of a plan with forward prefixes and float results run
+    // with double results (wide) and are rounded afterwards
+    const bool gf32 = f32 && plan->desc.trajectory != LQT_TRAJ_PREFIX;
     for (size_t j0 = 0; j0 < wave.size();) {
         size_t j1 = j0;
         int64_t nch = 0, max_nc = 0;
-        bool fwd = false;
+        bool fwd = false, m2 = false;
         while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
             nch += A.ginst_host[j1].NC;
             max_nc = std::max(max_nc, A.ginst_host[j1].NC);
-            fwd = fwd || want_fwd_c[j1];
+            fwd = fwd || want_fwd_c[j1] == 1;
+            m2 = m2 || want_fwd_c[j1] == 2;
             ++j1;
         }
         const lqt_problem& p0 = probs[wave[j0]];
         const int eng = eng_of(plan->route, p0);
-        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, f32, s,
-                                              plan->prof.on ? &hook : nullptr)
-                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, f32, s,
-                                             plan->prof.on ? &hook : nullptr);
+        const lqt::StageHook* hk = plan->prof.on ? &hook : nullptr;
+        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, gf32, s, hk)
+                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, gf32, s, hk);
+        if (e == hipSuccess && m2)
+            e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, s,
+                                hk);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
         j0 = j1;
+    }
+    // wide instances: double results rounded into the caller's float arrays
+    bool any_wide = false;
+    for (const WaveScratch& w : wsc) any_wide = any_wide || w.wide;
+    if (any_wide) {
+        if (plan->prof.on) Profiler::begin(&plan->prof, "narrow", s);
+        for (size_t j = 0; j < wave.size(); ++j) {
+            if (!wsc[j].wide) continue;
+            const lqt_problem& p = probs[wave[j]];
+            const lqt_outputs& o = outs[wave[j]];
+            const lqt::GInst& g = A.ginst_host[j];
+            const int64_t T = p.T, n = p.nx, m = p.nu;
+            const void* src[6] = {g.S, g.v, g.K, g.d, g.traj ? g.m2x : nullptr, g.traj ? g.m2u : nullptr};
+            void* dst[6] = {o.S, o.v, o.K, o.d, o.x, o.u};
+            const int64_t cnt[6] = {(T + 1) * n * n, (T + 1) * n, T * m * n, T * m, (T + 1) * n, T * m};
+            for (int i = 0; i < 6; ++i) {
+                if (!dst[i] || !src[i]) continue;
+                hipError_t e = lqt::convert_array(src[i], false, dst[i], true, cnt[i], s);
+                if (e != hipSuccess) return fail(plan, LQT_EHIP, "narrowing launch failed: %s", hipGetErrorString(e));
+            }
+        }
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
     }
     return post();
 }
@@ -701,15 +760,22 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
     } else {
         char* const ws = b + bs.small;
         char* const kd = ws + wave_bytes(plan, std_shape(p0));
-        const lqt::GInst gi = make_ginst(plan, p, o, ws, kd, 0, o.status);
+        const WaveScratch w = wave_scratch(plan, p0, o0, f32);
+        if (w.wide)
+            return fail(plan, LQT_ENOTSUP,
+                        "lqt_solve_noalloc: forward prefixes with float results on the chunked engines are "
+                        "provided by lqt_solve only");
+        const lqt::GInst gi = make_ginst(plan, p, o, ws, kd, 0, o.status, w);
         lqt::GInst* d_inst = (lqt::GInst*)(ws + bs.wave);
         k_put_inst<<<1, 64, 0, s>>>(gi, d_inst);
         hipError_t e = hipGetLastError();
-        const bool fwd = o.x || o.u;
+        const bool fwd = gi.x || gi.u;
         const int eng = eng_of(plan->route, p);
         if (e == hipSuccess)
             e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr)
                     : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, fwd, f32, s, nullptr);
+        if (e == hipSuccess && gi.traj)
+            e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p), d_inst, 1, gi.NC, s, nullptr);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
     }
     if (gen) {

@@ -132,8 +132,6 @@ def test_cross_term_or_reference_alone(api, plans, path, which):
 @pytest.mark.parametrize("traj", ["maps", "prefix"])
 @pytest.mark.parametrize("want", [("u",), ("K", "d"), ("x", "u"), ("S", "v", "u"), ("v", "u")])
 def test_partial_outputs(api, plans, path, traj, want):
-    if path == "wave" and traj == "prefix":
-        pytest.skip("the forward-prefix trajectory is provided on the lane pipeline only")
     n, m, T = (4, 3, 10000) if path == "small" else (8, 3, 500)
     route(plans, path=path)
     _say("gen cost outputs", want, path, traj)

@@ -3,7 +3,7 @@ nonlinear extension of Section IV-D) on the unicycle model of the nonlinear
 experiment (Section VI-E):
 lqt_nl_iterate against the oracle's linearise-and-solve iteration (pinned
 in tests/test_nonlinear_pins.py) with the same number of rounds, on the
-lane pipeline (both trajectory methods) and the wavefront engine, FP64 and
+lane pipeline and the wavefront engine (both trajectory methods), FP64 and
 MIXED, from the track start (converging) and from the constant-x_0 start,
 at T = 10^5 with the experiment's 10 rounds, plus the argument errors.
 
@@ -114,12 +114,13 @@ def test_lane_pipeline(api, plans, prec, traj, T, iters):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("traj", ["maps", "prefix"])
 @pytest.mark.parametrize("T,iters", [(300, 8), (1, 3), (64, 5), (2049, 4)])
-def test_wavefront_engine(api, plans, prec, T, iters):
+def test_wavefront_engine(api, plans, prec, traj, T, iters):
     route(plans, path="wave")
-    _say("unicycle wavefront engine T=", T, "rounds=", iters, prec)
+    _say("unicycle wavefront engine T=", T, "rounds=", iters, prec, traj)
     prob = inputs.unicycle_problem(T, seed=T % 89)
-    got = run(api, plans[(prec, "maps")], prob, iters, prec)
+    got = run(api, plans[(prec, traj)], prob, iters, prec)
     check(prec, got, reference(prob, iters, prec))
 
 
