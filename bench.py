@@ -99,8 +99,38 @@ def path_flops_per_step(n, m):
 
 
 def rel(a, b):
+    """Relative error over all steps stacked and, where it is larger, per step
+    (the largest step error against max(step size, RMS step size)); the
+    parity measure of the GPU tests."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
     nb = float(np.linalg.norm(b))
-    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    stacked = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    if a.ndim == 0 or a.shape[0] == 0:
+        return stacked
+    d = np.linalg.norm((a - b).reshape(a.shape[0], -1), axis=1)
+    ns = np.linalg.norm(b.reshape(b.shape[0], -1), axis=1)
+    rms = float(np.sqrt(np.mean(ns ** 2)))
+    step = float(np.max(d)) if rms == 0.0 else float(np.max(d / np.maximum(ns, rms)))
+    return max(stacked, step)
+
+
+def timing_stats(ms_list):
+    a = np.asarray(ms_list, dtype=np.float64)
+    return {"mean": round(float(a.mean()), 4), "median": round(float(np.median(a)), 4),
+            "p99": round(float(np.percentile(a, 99)), 4), "min": round(float(a.min()), 4), "runs": int(a.size)}
+
+
+def timed_solves(torch, stream, fn, runs):
+    """Per-solve device times (ms) of `runs` calls of fn, each bracketed by
+    events on the solve stream."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
 
 
 def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajectory="maps", cost="standard"):
@@ -189,7 +219,9 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
 def run_batched(args, api, inputs, torch, prec):
     """Uneven batch: 4096 instances, T log-uniform on [256, 16384], n in
     {4, 8, 16}, m = n / 2, diagonal costs, random-walk references; one
-    lqt_solve call per step (all instances, every output family)."""
+    lqt_solve call per step (all instances, every output family).  The
+    plan's chunk lengths are chosen by lqt_tune on the batch first (outside
+    the timed region, as plan creation)."""
     count = args.count
     shapes = inputs.batched_shapes(count)
     probs = [inputs.diag_problem(n, n // 2, T, 2, i) for i, (n, T) in enumerate(shapes)]
@@ -199,6 +231,7 @@ def run_batched(args, api, inputs, torch, prec):
     dps = [api.DeviceProblem(p) for p in probs]
     dos = [api.DeviceOutputs(p.n, p.m, p.T, dtype=dtype) for p in probs]
     stream = torch.cuda.current_stream(0)
+    tuned = plan.tune(dps, dos, stream) if not args.no_tune else None
     for _ in range(args.batched_warmup):
         plan.solve(dps, dos, stream)
     torch.cuda.synchronize()
@@ -207,31 +240,31 @@ def run_batched(args, api, inputs, torch, prec):
     if not args.no_parity:
         import oracle
 
-        worst = {f: 0.0 for f in api.FAMILIES}
-        for i in range(0, count, max(1, count // 16)):
-            ref = oracle.solve(probs[i])
-            got = dos[i].host()
-            for f in api.FAMILIES:
-                worst[f] = max(worst[f], rel(got[f], ref[f]))
+        # every size class sampled: 6 instances of each n, spread over the batch
+        worst = {}
+        for n in (4, 8, 16):
+            idx = [i for i, p in enumerate(probs) if p.n == n]
+            for i in idx[::max(1, len(idx) // 6)]:
+                ref = oracle.solve(probs[i])
+                got = dos[i].host()
+                w = worst.setdefault(f"n{n}", {f: 0.0 for f in api.FAMILIES})
+                for f in api.FAMILIES:
+                    w[f] = max(w[f], rel(got[f], ref[f]))
         rel_err = worst
     plan.profile(True)
     plan.profile_read()
     plan.solve(dps, dos, stream)
     stages = plan.profile_read()
     plan.profile(False)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.batched_steps):
-        plan.solve(dps, dos, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batched_steps
+    times = timed_solves(torch, stream, lambda: plan.solve(dps, dos, stream), args.batched_steps)
     plan.close()
+    st = timing_stats(times)
+    ms = st["mean"]
     return {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, m = n/2, T log-uniform "
                         f"[256, 16384], {prec}",
-            "steps_per_solve": steps_total, "ms_per_solve": round(ms, 3),
+            "steps_per_solve": steps_total, "ms_per_solve": ms, "ms_per_solve_stats": st,
             "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s", "status_failures": status_bad,
+            "tuned_chunk_divisors": tuned,
             "rel_err_sampled": rel_err,
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
 
@@ -563,8 +596,9 @@ def main():
     ap.add_argument("--fs-T", type=int, default=100_000)
     ap.add_argument("--fs-steps", type=int, default=20)
     ap.add_argument("--count", type=int, default=4096)
-    ap.add_argument("--batched-steps", type=int, default=3)
-    ap.add_argument("--batched-warmup", type=int, default=1)
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--batched-warmup", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="batched leg: keep the default chunk lengths")
     ap.add_argument("--dense-count", type=int, default=64)
     ap.add_argument("--dense-T", type=int, default=8192)
     ap.add_argument("--rate", type=float, default=2000.0)

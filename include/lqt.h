@@ -219,7 +219,9 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs
  * lqt_solve, lqt_tune, lqt_submit and lqt_nl_iterate calls; other plans are
  * not affected.  Every field 0 selects the automatic choice:
  *   path:       1 = the lane pipeline wherever it applies (nx <= 4, nu <= nx,
- *               any T), 2 = the chunked engines for every instance;
+ *               any T), 2 = the chunked engines for every instance, 3 = the
+ *               batched lane kernel wherever it applies (nx <= 4, nu <= nx,
+ *               time-invariant except c, any T);
  *   block:      1 = instances of the size classes 16 and 32 stay on the
  *               wavefront engine even when they are time-invariant;
  *   lane_chunk: steps per lane of the lane pipeline, 1..1024;

@@ -16,7 +16,7 @@ from . import _lib
 FAMILIES = ("S", "v", "K", "d", "x", "u")
 _PREC = {"fp64": _lib.PREC_FP64, "mixed": _lib.PREC_MIXED}
 _TRAJ = {"maps": _lib.TRAJ_MAPS, "prefix": _lib.TRAJ_PREFIX}
-_PATH = {None: 0, "auto": 0, "small": 1, "wave": 2}
+_PATH = {None: 0, "auto": 0, "small": 1, "wave": 2, "batch": 3}
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -198,8 +198,9 @@ class Plan:
     def set_routing(self, path: Optional[str] = None, wave_engine_only: bool = False, lane_chunk: int = 0,
                     wave_chunk: int = 0) -> None:
         """Routing and chunking overrides of this plan (lqt_set_routing):
-        path "small" (lane pipeline wherever it applies) or "wave" (chunked
-        engines), wave_engine_only keeps the classes 16/32 off the workgroup
+        path "small" (lane pipeline wherever it applies), "wave" (chunked
+        engines) or "batch" (batched lane kernel wherever it applies),
+        wave_engine_only keeps the classes 16/32 off the workgroup
         engines, lane_chunk / wave_chunk fix the chunk lengths (0: automatic).
         Called with no arguments it restores the automatic choices."""
         r = _lib.Routing(path=_PATH[path], block=1 if wave_engine_only else 0, lane_chunk=int(lane_chunk or 0),

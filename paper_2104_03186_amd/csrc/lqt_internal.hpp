@@ -86,6 +86,16 @@ hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, i
 // writes m2x, m2u); N = the group's size class (8, 16, 32, 64).
 hipError_t m2_chunked(int N, const GInst* d_inst, int ninst, int64_t nchunks, hipStream_t s, const StageHook* h);
 
+// Batched lane kernel (n <= 4, time-invariant except c): one workgroup of
+// 256 lanes per instance, chunks of lane_batch_chunk(T) steps.  mode: the
+// step-data mode of an instance, or -1 when the kernel does not take it.
+int lane_batch_mode(int n, int p, uint32_t per_step, bool has_c);
+int lane_batch_chunk(int64_t T);
+// Instances of one (n, m, mode) group; d_tab: device table of their
+// arguments (cst, K, d workspace filled in; NC, B from lane_batch_chunk).
+hipError_t lane_batch_solve(int n, int m, int mode, bool f32, const SmallArgs* d_tab, int ninst, hipStream_t s,
+                            const StageHook* h);
+
 bool small_supported(int n, int m);
 size_t small_cst_doubles(int n, int m, int p);
 size_t small_der_doubles(int n, int m);

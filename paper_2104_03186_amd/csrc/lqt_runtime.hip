@@ -33,16 +33,24 @@ constexpr int kServeSlots = 4;
 constexpr int kServeBatchMax = 512;
 constexpr int kDefaultQueue = 4096;
 
-// Path of an instance: a function of the instance and the plan's routing
-// overrides (never of the batch), so a result is the same alone and in any
-// mix.  Routing override 1 takes the lane pipeline wherever it applies, 2 the
-// chunked engines.
-enum class Path { Small, Wave };
+// Path of an instance: a function of the instance and the plan (routing
+// overrides, trajectory method), never of the batch, so a result is the same
+// alone and in any mix.  n <= 4 instances of horizon up to kBatchMaxT that
+// are time-invariant except c take the batched lane kernel (one workgroup
+// per instance) unless the plan recovers the trajectory by forward prefixes;
+// longer n <= 4 instances the lane pipeline; the rest the chunked engines.
+// Routing override 1 takes the lane pipeline wherever it applies, 2 the
+// chunked engines, 3 the batched lane kernel wherever it applies.
+enum class Path { Small, Wave, Batch };
+constexpr int64_t kBatchMaxT = 16384;
 
-Path path_of(const lqt_routing& R, const lqt_problem& p) {
+Path path_of(const lqt_routing& R, bool prefix, const lqt_problem& p) {
     const bool small_ok = lqt::small_supported(p.nx, p.nu);
+    const bool batch_ok = small_ok && lqt::lane_batch_mode(p.nx, p.ny, p.per_step, p.c != nullptr) >= 0;
     if (R.path == 1 && small_ok) return Path::Small;
     if (R.path == 2) return Path::Wave;
+    if (R.path == 3 && batch_ok) return Path::Batch;
+    if (batch_ok && p.T <= kBatchMaxT && !prefix) return Path::Batch;
     return (small_ok && p.T >= kSmallMinT) ? Path::Small : Path::Wave;
 }
 
@@ -144,7 +152,9 @@ struct Arena {
     bool owned = true;  // false: ws points into the serving pool
     lqt::GInst* ginst_host = nullptr;
     size_t ginst_cap = 0;
-    hipEvent_t ginst_done = nullptr;
+    lqt::SmallArgs* sargs_host = nullptr;  // batched-lane instance table (pinned)
+    size_t sargs_cap = 0;
+    hipEvent_t ginst_done = nullptr;       // both tables uploaded
 };
 
 // One batch of served requests in flight on its own stream.
@@ -192,6 +202,10 @@ struct lqt_plan_s {
 namespace {
 
 lqt_status fail(lqt_plan_t p, lqt_status code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+
+Path path_of(lqt_plan_t plan, const lqt_problem& p) {
+    return path_of(plan->route, plan->desc.trajectory == LQT_TRAJ_PREFIX, p);
+}
 
 lqt_status fail(lqt_plan_t p, lqt_status code, const char* fmt, ...) {
     char buf[512];
@@ -330,30 +344,43 @@ size_t gen_bytes(const lqt_problem& p, const lqt_outputs& o) {
     return b;
 }
 
+// Workspace of one batched-lane instance: its constants, and the double gains
+// when the caller does not take K and d (the kernel always writes them).
+size_t batch_bytes(const lqt_problem& p, const lqt_outputs& o) {
+    size_t b = align_up(lqt::small_cst_doubles(p.nx, p.nu, std::max(p.ny, 1)) * sizeof(double));
+    if (!o.K || !o.d) b += align_up((size_t)p.T * (p.nu * p.nx + p.nu) * sizeof(double));
+    return b;
+}
+
 // Device bytes of one launch group: the transform regions of generalised
 // instances, then the small-path instances, which run one after another in
 // one region (the largest), each wavefront-path instance's own region, then
-// the instance table.
+// the instance table, then the batched-lane instances and their table.
 struct BatchSize {
     lqt_plan_t plan = nullptr;
-    size_t gen = 0, small = 0, wave = 0;
-    size_t nwave = 0;
+    size_t gen = 0, small = 0, wave = 0, batch = 0;
+    size_t nwave = 0, nbatch = 0;
     bool f32 = false;  // float results
     BatchSize(lqt_plan_t pl, bool f) : plan(pl), f32(f) {}
     explicit BatchSize(lqt_plan_t pl) : plan(pl), f32(pl->desc.prec == LQT_PREC_MIXED) {}
     void add(const lqt_problem& p0, const lqt_outputs& o) {
         gen += gen_bytes(p0, o);
         const lqt_problem p = std_shape(p0);
-        if (path_of(plan->route, p) == Path::Small) {
+        const Path path = path_of(plan, p);
+        if (path == Path::Small) {
             const bool m2 = plan->desc.trajectory == LQT_TRAJ_PREFIX && (o.x || o.u);
             small = std::max(small,
                              align_up(layout_for(plan->route, p, !o.K, !o.d, m2, !o.S, !o.v, m2 && f32).total));
+        } else if (path == Path::Batch) {
+            batch += batch_bytes(p, o);
+            ++nbatch;
         } else {
             wave += wave_bytes(plan, p) + wave_scratch(plan, p0, o, f32).total();
             ++nwave;
         }
     }
-    size_t total() const { return gen + small + (nwave ? wave + align_up(nwave * sizeof(lqt::GInst)) : 0); }
+    size_t wave_end() const { return gen + small + (nwave ? wave + align_up(nwave * sizeof(lqt::GInst)) : 0); }
+    size_t total() const { return wave_end() + (nbatch ? batch + align_up(nbatch * sizeof(lqt::SmallArgs)) : 0); }
 };
 
 lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o, int idx) {
@@ -364,7 +391,7 @@ lqt_status validate(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o,
     if (p.nx > plan->desc.max_nx || p.nu > plan->desc.max_nu)
         return fail(plan, LQT_EINVAL, "instance %d: nx=%d nu=%d exceed the plan's max_nx=%d max_nu=%d", idx, p.nx,
                     p.nu, plan->desc.max_nx, plan->desc.max_nu);
-    if (path_of(plan->route, p) == Path::Wave) {
+    if (path_of(plan, p) == Path::Wave) {
         if (std::max(std::max(p.nx, p.nu), std::max(p.ny, p.nyT)) > kWaveMaxN)
             return fail(plan, LQT_ENOTSUP, "instance %d: dimensions nx=%d nu=%d ny=%d nyT=%d exceed %d", idx, p.nx,
                         p.nu, p.ny, p.nyT, kWaveMaxN);
@@ -536,6 +563,27 @@ lqt::GInst make_ginst(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& 
     return g;
 }
 
+// Arguments of one batched-lane instance whose workspace (batch_bytes)
+// starts at ws.
+lqt::SmallArgs make_batch_args(const lqt_problem& p, const lqt_outputs& o, char* ws, int32_t* status, bool f32) {
+    lqt::SmallArgs a{};
+    a.F = p.F; a.c = p.c; a.L = p.L; a.U = p.U; a.H = p.H; a.X = p.X; a.r = p.r;
+    a.HT = p.HT; a.XT = p.XT; a.rT = p.rT; a.x0 = p.x0;
+    a.T = p.T; a.n = p.nx; a.m = p.nu; a.p = p.ny; a.pT = p.nyT;
+    a.per_step = p.per_step & (p.c ? 63u : (63u & ~(uint32_t)LQT_PS_c));
+    a.cst = (double*)ws;
+    double* kd = (double*)(ws + align_up(lqt::small_cst_doubles(p.nx, p.nu, std::max(p.ny, 1)) * sizeof(double)));
+    a.S = o.S; a.v = o.v; a.x = o.x; a.u = o.u;
+    a.K = o.K ? o.K : (void*)kd;  // sized for double gains; float ones use part of it
+    a.d = o.d ? o.d : (void*)(kd + (size_t)p.T * p.nu * p.nx);
+    a.status = status;
+    a.f32 = f32 ? 1 : 0;
+    a.B = lqt::lane_batch_chunk(p.T);
+    a.NC = (p.T + a.B - 1) / a.B;
+    a.want_fwd = (o.x || o.u) ? 1 : 0;
+    return a;
+}
+
 // Solve a set of instances on stream s in arena A.  status_override (if not
 // null) gives per-instance device status words used instead of outs[i].status.
 // Results are float when f32 is set (the plan's precision unless the caller
@@ -544,8 +592,11 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
                      hipStream_t s, int32_t* const* status_override, int f32_override = -1) {
     const bool f32 = f32_override < 0 ? plan->desc.prec == LQT_PREC_MIXED : f32_override != 0;
     // partition by path; wavefront instances ordered by size class
-    std::vector<int> small, wave;
-    for (int i = 0; i < count; ++i) (path_of(plan->route, probs[i]) == Path::Small ? small : wave).push_back(i);
+    std::vector<int> small, wave, batch;
+    for (int i = 0; i < count; ++i) {
+        const Path path = path_of(plan, probs[i]);
+        (path == Path::Small ? small : (path == Path::Batch ? batch : wave)).push_back(i);
+    }
     // launch groups: (size class, engine)
     auto cls = [&](int i) {
         const int e = eng_of(plan->route, probs[i]);
@@ -604,9 +655,55 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         st = launch_one(plan, base, probs[i], outs[i], s, status_override ? status_override[i] : nullptr, f32);
         if (st != LQT_OK) return st;
     }
+    if ((!batch.empty() || !wave.empty()) && A.ginst_done)
+        (void)hipEventSynchronize(A.ginst_done);  // the previous upload has left the host tables
+    if (!batch.empty()) {
+        // one launch pair per (n, m, step-data mode) group
+        auto bkey = [&](int i) {
+            const lqt_problem& p = probs[i];
+            return (p.nx * 8 + p.nu) * 4 + lqt::lane_batch_mode(p.nx, p.ny, p.per_step, p.c != nullptr);
+        };
+        std::stable_sort(batch.begin(), batch.end(), [&](int a, int b) { return bkey(a) < bkey(b); });
+        if (A.sargs_cap < batch.size()) {
+            if (A.sargs_host) (void)hipHostFree(A.sargs_host);
+            A.sargs_host = nullptr;
+            A.sargs_cap = 0;
+            const size_t cap = std::max<size_t>(batch.size(), 256);
+            if (hipHostMalloc((void**)&A.sargs_host, cap * sizeof(lqt::SmallArgs), 0) != hipSuccess)
+                return fail(plan, LQT_ENOMEM, "pinned instance table allocation failed");
+            A.sargs_cap = cap;
+        }
+        char* const bbase = A.ws + bs.wave_end();
+        size_t off = 0;
+        for (size_t j = 0; j < batch.size(); ++j) {
+            A.sargs_host[j] = make_batch_args(probs[batch[j]], outs[batch[j]], bbase + off,
+                                              status_override ? status_override[batch[j]] : outs[batch[j]].status,
+                                              f32);
+            off += batch_bytes(probs[batch[j]], outs[batch[j]]);
+        }
+        lqt::SmallArgs* d_tab = (lqt::SmallArgs*)(bbase + bs.batch);
+        if (hipMemcpyAsync(d_tab, A.sargs_host, batch.size() * sizeof(lqt::SmallArgs), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(plan, LQT_EHIP, "instance table upload failed");
+        lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
+        for (size_t j0 = 0; j0 < batch.size();) {
+            size_t j1 = j0;
+            while (j1 < batch.size() && bkey(batch[j1]) == bkey(batch[j0])) ++j1;
+            const lqt_problem& p0 = probs[batch[j0]];
+            hipError_t e = lqt::lane_batch_solve(p0.nx, p0.nu, lqt::lane_batch_mode(p0.nx, p0.ny, p0.per_step,
+                                                                                   p0.c != nullptr),
+                                                 f32, d_tab + j0, (int)(j1 - j0), s, plan->prof.on ? &hook : nullptr);
+            if (e != hipSuccess) return fail(plan, LQT_EHIP, "batched lane launch failed: %s", hipGetErrorString(e));
+            j0 = j1;
+        }
+        if (wave.empty()) {
+            if (!A.ginst_done && hipEventCreateWithFlags(&A.ginst_done, hipEventDisableTiming) != hipSuccess)
+                return fail(plan, LQT_EHIP, "event creation failed");
+            (void)hipEventRecord(A.ginst_done, s);
+        }
+    }
     if (wave.empty()) return post();
     if (A.ginst_cap < wave.size()) {
-        if (A.ginst_done) (void)hipEventSynchronize(A.ginst_done);
         if (A.ginst_host) (void)hipHostFree(A.ginst_host);
         A.ginst_host = nullptr;
         A.ginst_cap = 0;
@@ -614,8 +711,6 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         if (hipHostMalloc((void**)&A.ginst_host, cap * sizeof(lqt::GInst), 0) != hipSuccess)
             return fail(plan, LQT_ENOMEM, "pinned instance table allocation failed");
         A.ginst_cap = cap;
-    } else if (A.ginst_done) {
-        (void)hipEventSynchronize(A.ginst_done);  // previous upload has left the buffer
     }
     char* wbase = base + bs.small;
     std::vector<char> want_fwd_c(wave.size(), 0);
@@ -733,6 +828,10 @@ __global__ void k_put_inst(lqt::GInst g, lqt::GInst* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = g;
 }
 
+__global__ void k_put_sargs(lqt::SmallArgs a, lqt::SmallArgs* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}
+
 // One instance solved with its whole workspace in [base, base + cap): the
 // regions of solve_all for a batch of one, the instance table included.
 // Enqueues kernels only: no device or host allocation, no events.
@@ -755,8 +854,19 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
         if ((st = gen_prepare(plan, base, off, p0, o0, p, o, f32, s, g)) != LQT_OK) return st;
     }
     char* const b = base + bs.gen;
-    if (path_of(plan->route, p) == Path::Small) {
+    const Path path = path_of(plan, p);
+    if (path == Path::Small) {
         if ((st = launch_one(plan, b, p, o, s, nullptr, f32, false)) != LQT_OK) return st;
+    } else if (path == Path::Batch) {
+        char* const bb = base + bs.wave_end();
+        const lqt::SmallArgs a = make_batch_args(p, o, bb, o.status, f32);
+        lqt::SmallArgs* d_tab = (lqt::SmallArgs*)(bb + bs.batch);
+        k_put_sargs<<<1, 64, 0, s>>>(a, d_tab);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = lqt::lane_batch_solve(p.nx, p.nu, lqt::lane_batch_mode(p.nx, p.ny, p.per_step, p.c != nullptr), f32,
+                                      d_tab, 1, s, nullptr);
+        if (e != hipSuccess) return fail(plan, LQT_EHIP, "batched lane launch failed: %s", hipGetErrorString(e));
     } else {
         char* const ws = b + bs.small;
         char* const kd = ws + wave_bytes(plan, std_shape(p0));
@@ -788,6 +898,7 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
 void arena_release(Arena& A) {
     if (A.ginst_done) (void)hipEventDestroy(A.ginst_done);
     if (A.ginst_host) (void)hipHostFree(A.ginst_host);
+    if (A.sargs_host) (void)hipHostFree(A.sargs_host);
     if (A.owned && A.ws) (void)hipFree(A.ws);
     A = Arena{};
 }
@@ -1119,7 +1230,7 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
         std::vector<lqt_problem> ps;
         std::vector<lqt_outputs> os;
         for (int i = 0; i < count; ++i)
-            if (path_of(plan->route, probs[i]) == Path::Wave && group_key(plan->route, probs[i]) == key) {
+            if (path_of(plan, probs[i]) == Path::Wave && group_key(plan->route, probs[i]) == key) {
                 ps.push_back(probs[i]);
                 os.push_back(outs[i]);
             }
@@ -1161,7 +1272,7 @@ lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing* routing) {
         return LQT_OK;
     }
     const lqt_routing& r = *routing;
-    if (r.path < 0 || r.path > 2 || r.block < 0 || r.block > 1 || r.lane_chunk < 0 || r.lane_chunk > 1024 ||
+    if (r.path < 0 || r.path > 3 || r.block < 0 || r.block > 1 || r.lane_chunk < 0 || r.lane_chunk > 1024 ||
         r.wave_chunk < 0 || r.wave_chunk > 4096)
         return fail(plan, LQT_EINVAL, "lqt_set_routing: path=%d block=%d lane_chunk=%d wave_chunk=%d out of range",
                     r.path, r.block, r.lane_chunk, r.wave_chunk);
