@@ -491,31 +491,43 @@ def run_copy(args, torch):
 def run_serving(args, api, inputs, torch, prec):
     """Poisson arrivals (args.rate req/s for args.serve_seconds s), nx ~ U{4..32},
     nu = ceil(nx / 2), T log-uniform on [64, 65536], diagonal costs and
-    random-walk references; each request asks for K, d, x, u.  The first
-    args.pool requests of the stream are generated and kept on the device;
-    request i replays entry i % pool (its shape is that entry's)."""
+    random-walk references; each request asks for K, d, x, u.  One instance
+    of T = 65536 per nx is kept on the device and every request solves its
+    own horizon as a prefix of it, so every request has its own (nx, T);
+    outputs are allocated per request.  Latency: submit to completed poll."""
     reqs = inputs.serving_requests(args.rate, args.serve_seconds)
-    P = min(args.pool, len(reqs))
     dtype = torch.float64 if prec == "fp64" else torch.float32
     want = ("K", "d", "x", "u")
-    ent = []
-    for j in range(P):
-        _, n, m, T = reqs[j]
-        p = inputs.diag_problem(n, m, T, 4, j)
-        ent.append((p, api.DeviceProblem(p), api.DeviceOutputs(n, m, T, dtype=dtype, want=want, status=False)))
+    Tmax = 65536
+    base = {}
+    for n in range(4, 33):
+        p = inputs.diag_problem(n, (n + 1) // 2, Tmax, 4, n)
+        base[n] = (p, api.DeviceProblem(p))
     torch.cuda.synchronize()
     plan = api.Plan(32, 16, prec=prec, device=0, hbm_budget_bytes=args.serve_pool_gb << 30)
-    # warm-up: the first requests of the pool, once
-    tick = [plan.submit(ent[j][1], ent[j][2]) for j in range(min(P, 16))]
-    for t in tick:
+
+    def wait(t):
         while plan.poll(t) is None:
             pass
+
+    # warm-up, then the latency of representative shapes served alone
+    for n in (4, 16, 32):
+        o = api.DeviceOutputs(n, (n + 1) // 2, 512, dtype=dtype, want=want, status=False)
+        wait(plan.submit(base[n][1], o, T=512))
+    alone = {}
+    for n, T in ((4, 64), (4, 65536), (8, 1024), (16, 1024), (16, 65536), (32, 64), (32, 4096), (32, 65536)):
+        ts = []
+        for _ in range(5):
+            o = api.DeviceOutputs(n, (n + 1) // 2, T, dtype=dtype, want=want, status=False)
+            t0 = time.perf_counter()
+            wait(plan.submit(base[n][1], o, T=T))
+            ts.append((time.perf_counter() - t0) * 1e3)
+        alone[f"n{n}_T{T}"] = round(float(np.median(ts)), 3)
     N = len(reqs)
-    busy = [False] * P
     inflight = {}
-    lat = []
+    lat, lat_short, lat_long = [], [], []
     served_steps = 0
-    waits = 0
+    keep = {}  # a few cheap requests kept for the parity check
     i = 0
     t0 = time.perf_counter()
     last_done = 0.0
@@ -526,49 +538,56 @@ def run_serving(args, api, inputs, torch, prec):
             print(f"[serving] t={now:.1f}s submitted={i}/{N} in_flight={len(inflight)}", file=sys.stderr, flush=True)
             next_note += 5.0
         while i < N and reqs[i][0] <= now:
-            e = i % P
-            if busy[e]:
-                waits += 1
-                break
-            tk = plan.submit(ent[e][1], ent[e][2])
-            inflight[tk] = (reqs[i][0], e)
-            busy[e] = True
+            _, n, m, T = reqs[i]
+            o = api.DeviceOutputs(n, m, T, dtype=dtype, want=want, status=False)
+            tk = plan.submit(base[n][1], o, T=T)
+            inflight[tk] = (reqs[i][0], n, T, o, i)
             i += 1
         for tk in list(inflight):
             st = plan.poll(tk)
             if st is not None:
                 t_done = time.perf_counter() - t0
-                arr, e = inflight.pop(tk)
+                arr, n, T, o, idx = inflight.pop(tk)
                 if st != 0:
                     raise RuntimeError(f"served request failed with status {st}")
-                lat.append(t_done - arr)
-                served_steps += ent[e][0].T
-                busy[e] = False
+                ms = (t_done - arr) * 1e3
+                lat.append(ms)
+                (lat_long if T >= 4096 else lat_short).append(ms)
+                served_steps += T
                 last_done = t_done
+                if len(keep) < 4 and n ** 3 * T < 4e6:
+                    keep[idx] = (n, T, o)
     stats = plan.serve_stats()
     plan.close()
-    lat_ms = np.array(lat) * 1e3
+    lat_ms = np.array(lat)
     offered = sum(r[3] for r in reqs) / args.serve_seconds
     rel_err = None
     if not args.no_parity:
         import oracle
 
-        # the four cheapest entries (oracle cost ~ n^3 T) against the oracle
-        order = sorted(range(P), key=lambda j: ent[j][0].n ** 3 * ent[j][0].T)[:4]
         worst = {f: 0.0 for f in want}
-        for j in order:
-            ref = oracle.solve(ent[j][0])
-            got = ent[j][2].host()
+        for idx, (n, T, o) in keep.items():
+            p = inputs.diag_problem(n, (n + 1) // 2, Tmax, 4, n)
+            sub = inputs.prefix_problem(p, T)
+            ref = oracle.solve(sub)
+            got = o.host()
             for f in want:
                 worst[f] = max(worst[f], rel(got[f], ref[f]))
         rel_err = worst
+
+    def pct(a, q):
+        return round(float(np.percentile(np.asarray(a), q)), 3) if len(a) else None
+
     return {"workload": f"serving: Poisson {args.rate:g} req/s for {args.serve_seconds:g} s, nx ~ U{{4..32}}, "
                         f"nu = ceil(nx/2), T log-uniform [64, 65536], {prec}, outputs K d x u",
-            "requests": len(lat), "distinct_requests_on_device": P,
-            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-            "max_ms": round(float(lat_ms.max()), 3), "served_steps_per_s": round(served_steps / last_done, 1),
+            "requests": len(lat), "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
+            "max_ms": round(float(lat_ms.max()), 3),
+            "p50_p99_ms_T_below_4096": [pct(lat_short, 50), pct(lat_short, 99)],
+            "p50_p99_ms_T_from_4096": [pct(lat_long, 50), pct(lat_long, 99)],
+            "alone_ms_by_shape": alone,
+            "served_steps_per_s": round(served_steps / last_done, 1),
             "offered_steps_per_s": round(offered, 1), "elapsed_s": round(last_done, 3),
-            "submit_waits_on_busy_entry": waits, "serve_stats": stats, "rel_err_sampled": rel_err}
+            "serve_stats": stats, "rel_err_sampled": rel_err}
 
 
 def main():
@@ -602,8 +621,7 @@ def main():
     ap.add_argument("--dense-count", type=int, default=64)
     ap.add_argument("--dense-T", type=int, default=8192)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--pool", type=int, default=512)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-pool-gb", type=int, default=16)
     args = ap.parse_args()
 

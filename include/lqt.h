@@ -239,17 +239,26 @@ typedef struct {
 lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing *routing);
 
 /* Serving interface (continuous batching).  lqt_submit queues one instance
- * and returns at once with *ticket.  Queued requests are launched in FIFO
- * order as batches: whenever one of the plan's serving streams is idle, the
- * longest prefix of the queue whose workspace fits one free range of the
- * plan's serving pool (hbm_budget_bytes, or 8 GiB when that is 0) becomes one
- * batch on that stream.  Several batches run on the device at once; a
- * request that arrives while others are running joins the next batch as soon
- * as a stream and pool memory are free.  Batching never changes a result:
- * every instance is solved exactly as by lqt_solve alone.  Progress is made
- * inside lqt_submit and lqt_poll.
+ * and returns at once with *ticket.  Requests wait in one FIFO per lane:
+ * short solves (the batched lane kernel, the lane pipeline, and chunked
+ * solves with a short critical path) and long ones (chunked solves of long
+ * horizon or large size class); each of the plan's serving streams belongs to
+ * one lane, so a short request is never batched with, or queued behind, a
+ * long one.  Whenever a stream is idle, the longest prefix of its lane's
+ * queue whose workspace fits one free range of the plan's serving pool
+ * (hbm_budget_bytes, or 8 GiB when that is 0) becomes one batch on that
+ * stream.  Several batches run on the device at once; a request that arrives
+ * while others are running joins the next batch of its lane as soon as a
+ * stream and pool memory are free.  Nothing overtakes the head of a lane;
+ * a head waiting for memory is protected (the other lane launches only
+ * batches that leave it room), so no request starves.  Batching never
+ * changes a result: every instance is solved exactly as by lqt_solve alone.
+ * Progress is made inside lqt_submit and lqt_poll and by a progress thread
+ * of the plan (started by the first lqt_submit, stopped by lqt_destroy).
  *   LQT_ENOMEM: the request alone needs more than the serving pool.
  *   LQT_EBUSY:  max_inflight requests are already queued or running.
+ * Once a request is queued, lqt_submit returns LQT_OK; a failure to launch
+ * its batch is its status, returned by lqt_poll.
  * The caller's input and output buffers must stay valid until lqt_poll has
  * returned something other than LQT_EAGAIN for the ticket. */
 lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem *prob, const lqt_outputs *out,

@@ -36,9 +36,15 @@ class DeviceProblem:
             a = getattr(prob, f, None)  # M, s: generalised stage cost (Section IV-D)
             self.t[f] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
 
-    def struct(self) -> _lib.Problem:
+    def struct(self, T: Optional[int] = None) -> _lib.Problem:
+        """The C struct; T (<= self.T) takes the instance over its first T
+        steps (per-step arrays read as prefixes; the terminal data unchanged)."""
         s = _lib.Problem()
-        s.nx, s.nu, s.ny, s.nyT, s.T, s.per_step = self.n, self.m, self.p, self.pT, self.T, self.per_step
+        if T is None:
+            T = self.T  # passed as given: the library validates it
+        elif not 1 <= int(T) <= self.T:
+            raise ValueError(f"prefix T={T} outside 1..{self.T}")
+        s.nx, s.nu, s.ny, s.nyT, s.T, s.per_step = self.n, self.m, self.p, self.pT, T, self.per_step
         for f in self.FIELDS:
             setattr(s, f, _ptr(self.t[f]))
         return s
@@ -243,10 +249,12 @@ class Plan:
         _lib.check(_lib.load().lqt_fs_solve(self._h, ctypes.byref(ps), ctypes.byref(os_),
                                             ctypes.c_void_p(stream.cuda_stream)), self._h)
 
-    def submit(self, prob: DeviceProblem, out: DeviceOutputs) -> int:
+    def submit(self, prob: DeviceProblem, out: DeviceOutputs, T: Optional[int] = None) -> int:
+        """Queue one instance (lqt_submit); T: solve the instance's first T
+        steps (out sized for T).  Returns the ticket."""
         self._check_dtype(out)
         t = ctypes.c_uint64()
-        ps, os_ = prob.struct(), out.struct()
+        ps, os_ = prob.struct(T), out.struct()
         _lib.check(_lib.load().lqt_submit(self._h, ctypes.byref(ps), ctypes.byref(os_), ctypes.byref(t)), self._h)
         return int(t.value)
 

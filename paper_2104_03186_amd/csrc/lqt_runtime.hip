@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -13,11 +15,13 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/lqt.h"
 #include "lqt_internal.hpp"
+#include "lqt_serve.hpp"
 #include "lqt_ws.hpp"
 
 namespace {
@@ -157,22 +161,30 @@ struct Arena {
     hipEvent_t ginst_done = nullptr;       // both tables uploaded
 };
 
-// One batch of served requests in flight on its own stream.
+// Device side of one serving slot: its stream, its batch's arena (a range of
+// the serving pool), status words and completion event.
 struct Slot {
     hipStream_t stream = nullptr;
     Arena arena;
     int32_t* status_dev = nullptr;   // [kServeBatchMax] per-request status words
     int32_t* status_host = nullptr;  // pinned copy, valid once `done` has fired
     hipEvent_t done = nullptr;
-    bool busy = false;
-    size_t off = 0, len = 0;         // range of the serving pool
-    std::vector<uint64_t> tickets;
 };
 
 struct PendingReq {
-    uint64_t ticket;
     lqt_problem p;
     lqt_outputs o;
+};
+
+// The device operations of the serving core (lqt_serve.hpp).
+struct ServeOps {
+    lqt_plan_t plan = nullptr;
+    struct Acc;
+    Acc acc();
+    int launch(int slot, const size_t* req, size_t count, size_t off, size_t len);
+    int query(int slot);
+    int status(int slot, size_t i);
+    void drain(int slot);
 };
 
 struct lqt_plan_s {
@@ -181,16 +193,17 @@ struct lqt_plan_s {
     Arena main;
     std::string err;
     std::recursive_mutex mu;
-    // serving state
+    // serving state: device pool and slots, the host admission core, the
+    // payloads of queued requests (by ticket), and the progress thread
     char* pool = nullptr;
-    size_t pool_size = 0;
-    std::map<size_t, size_t> free_ranges;  // offset -> length
     std::vector<Slot> slots;
-    std::deque<PendingReq> pending;
-    std::unordered_map<uint64_t, int> state;  // ticket -> -1 queued/running, else final status
-    size_t live = 0;                          // queued + running requests
+    lqt::ServeCore<ServeOps> core;
+    ServeOps ops;
+    std::unordered_map<uint64_t, PendingReq> payload;
     uint64_t next_ticket = 1;
-    lqt_serve_stats stats{};
+    std::thread progress;
+    std::condition_variable_any wake;
+    bool stop = false;
     int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
     lqt_routing route{};                          // routing and chunking overrides (lqt_set_routing)
     lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
@@ -905,11 +918,12 @@ void arena_release(Arena& A) {
 
 // ---- serving: continuous batching -----------------------------------------
 //
-// Requests wait in a FIFO.  Whenever a slot (stream) is idle, the longest
-// prefix of the queue whose workspace fits one free range of the device pool
-// is launched on it as one batch.  Up to kServeSlots batches run at once on
-// the device; a finished batch returns its range and slot, and the next batch
-// takes whatever has arrived in the meantime.
+// The admission logic (per-lane FIFOs, batches as long FIFO prefixes that fit
+// one free range of the pool, slots owned by lanes) is the host-only core of
+// lqt_serve.hpp; the operations below are its device side.  Progress is made
+// inside lqt_submit and lqt_poll and by a progress thread of the plan, so
+// queued requests are launched and finished batches retired also while the
+// caller does neither.
 
 size_t serve_bytes(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o) {
     BatchSize b(plan);
@@ -917,40 +931,74 @@ size_t serve_bytes(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& o) 
     return b.total();
 }
 
-bool pool_take(lqt_plan_t plan, size_t len, size_t& off) {
-    for (auto it = plan->free_ranges.begin(); it != plan->free_ranges.end(); ++it) {
-        if (it->second >= len) {
-            off = it->first;
-            const size_t rest = it->second - len;
-            plan->free_ranges.erase(it);
-            if (rest) plan->free_ranges[off + len] = rest;
-            return true;
-        }
-    }
-    return false;
+// Lane of a request: 1 (long) when its critical path is long -- the chunked
+// engines walk about 3 B + NC steps in sequence (fold, chain, down-sweep,
+// roll-out) at a cost that grows with the size class -- else 0.
+int serve_lane(lqt_plan_t plan, const lqt_problem& p0) {
+    const lqt_problem p = std_shape(p0);
+    if (path_of(plan, p) != Path::Wave) return 0;  // one launch sequence of short walks
+    const int64_t B = chunk_for(plan, p), NC = (p.T + B - 1) / B;
+    return (3 * B + NC) * (int64_t)tile_class_of(p) > 4096 ? 1 : 0;
 }
 
-size_t pool_largest(lqt_plan_t plan) {
-    size_t b = 0;
-    for (auto& kv : plan->free_ranges) b = std::max(b, kv.second);
-    return b;
+}  // namespace
+
+struct ServeOps::Acc {
+    BatchSize bs;
+    lqt_plan_t plan;
+    explicit Acc(lqt_plan_t pl) : bs(pl), plan(pl) {}
+    void add(size_t h) {
+        const PendingReq& r = plan->payload.at(h);
+        bs.add(r.p, r.o);
+    }
+    size_t total() const { return bs.total(); }
+};
+
+ServeOps::Acc ServeOps::acc() { return Acc(plan); }
+
+int ServeOps::launch(int si, const size_t* req, size_t count, size_t off, size_t len) {
+    Slot& s = plan->slots[si];
+    std::vector<lqt_problem> ps(count);
+    std::vector<lqt_outputs> os(count);
+    std::vector<int32_t*> ovr(count);
+    for (size_t i = 0; i < count; ++i) {
+        auto it = plan->payload.find(req[i]);
+        ps[i] = it->second.p;
+        os[i] = it->second.o;
+        ovr[i] = s.status_dev + i;
+        plan->payload.erase(it);  // the batch's launch takes what it needs
+    }
+    s.arena.ws = plan->pool + off;
+    s.arena.cap = len;
+    lqt_status st = solve_all(plan, s.arena, ps.data(), os.data(), (int32_t)count, s.stream, ovr.data());
+    if (st == LQT_OK &&
+        hipMemcpyAsync(s.status_host, s.status_dev, count * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream) !=
+            hipSuccess)
+        st = fail(plan, LQT_EHIP, "status copy failed");
+    for (size_t i = 0; st == LQT_OK && i < count; ++i)
+        if (os[i].status &&
+            hipMemcpyAsync(os[i].status, s.status_dev + i, sizeof(int32_t), hipMemcpyDefault, s.stream) != hipSuccess)
+            st = fail(plan, LQT_EHIP, "status copy failed");
+    if (st == LQT_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = fail(plan, LQT_EHIP, "event record failed");
+    return st;
 }
 
-void pool_give(lqt_plan_t plan, size_t off, size_t len) {
-    auto it = plan->free_ranges.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != plan->free_ranges.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        plan->free_ranges.erase(nx);
-    }
-    if (it != plan->free_ranges.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-            pv->second += it->second;
-            plan->free_ranges.erase(it);
-        }
-    }
+int ServeOps::query(int si) {
+    const hipError_t q = hipEventQuery(plan->slots[si].done);
+    if (q == hipSuccess) return 1;
+    (void)hipGetLastError();
+    return q == hipErrorNotReady ? 0 : -1;
 }
+
+int ServeOps::status(int si, size_t i) { return plan->slots[si].status_host[i]; }
+
+void ServeOps::drain(int si) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(plan->slots[si].stream);
+    (void)hipGetLastError();
+}
+
+namespace {
 
 void slot_release(Slot& s) {
     if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -959,6 +1007,23 @@ void slot_release(Slot& s) {
     if (s.status_host) (void)hipHostFree(s.status_host);
     arena_release(s.arena);
     s = Slot{};
+}
+
+// Progress thread: retires finished batches and launches queued requests
+// every ~50 us while work is in flight; sleeps until a submit otherwise.
+void serve_progress(lqt_plan_t plan) {
+    (void)hipSetDevice(plan->desc.device);
+    std::unique_lock<std::recursive_mutex> lk(plan->mu);
+    while (!plan->stop) {
+        (void)plan->core.pump(plan->ops);
+        if (plan->core.idle()) {
+            plan->wake.wait_for(lk, std::chrono::milliseconds(20));
+        } else {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            lk.lock();
+        }
+    }
 }
 
 // All or nothing: the pool and every slot exist afterwards, or none of them
@@ -990,107 +1055,13 @@ lqt_status serve_init(lqt_plan_t plan) {
         return fail(plan, LQT_EHIP, "serving slot set-up failed");
     }
     plan->slots = std::move(slots);
-    plan->pool_size = want;
-    plan->free_ranges.clear();
-    plan->free_ranges[0] = want;
-    plan->stats.pool_bytes = want;
+    std::vector<int> lanes(kServeSlots);
+    for (int i = 0; i < kServeSlots; ++i) lanes[i] = i < kServeSlots / 2 ? 0 : 1;  // half short, half long
+    plan->core.init(want, lanes, kServeBatchMax, plan->desc.max_inflight);
+    plan->ops.plan = plan;
     plan->pool = (char*)p;
-    return LQT_OK;
-}
-
-// Give a slot's batch back: its requests' final states (`code` for all of
-// them, or the copied status words when code < 0), its pool range, the slot.
-void slot_retire(lqt_plan_t plan, Slot& s, int code) {
-    for (size_t i = 0; i < s.tickets.size(); ++i) plan->state[s.tickets[i]] = code < 0 ? s.status_host[i] : code;
-    plan->live -= s.tickets.size();
-    plan->stats.completed += (int64_t)s.tickets.size();
-    plan->stats.running_batches -= 1;
-    plan->stats.pool_in_use -= s.len;
-    s.tickets.clear();
-    pool_give(plan, s.off, s.len);
-    s.busy = false;
-}
-
-// Retire finished batches, then launch queued requests on idle slots.
-lqt_status serve_pump(lqt_plan_t plan) {
-    for (Slot& s : plan->slots) {
-        if (!s.busy) continue;
-        hipError_t q = hipEventQuery(s.done);
-        if (q == hipErrorNotReady) {
-            (void)hipGetLastError();
-            continue;
-        }
-        if (q != hipSuccess) {
-            // the batch's outcome is unknown: its requests fail, and its
-            // range is reused only once nothing queued on the stream runs
-            (void)hipGetLastError();
-            (void)hipStreamSynchronize(s.stream);
-            (void)hipGetLastError();
-            slot_retire(plan, s, LQT_EHIP);
-            return fail(plan, LQT_EHIP, "serving batch failed: %s", hipGetErrorString(q));
-        }
-        slot_retire(plan, s, -1);
-    }
-    for (Slot& s : plan->slots) {
-        if (plan->pending.empty()) break;
-        if (s.busy || !s.stream || !s.done || !s.status_dev || !s.status_host) continue;
-        const size_t room = pool_largest(plan);
-        BatchSize bs(plan);
-        size_t take = 0;
-        while (take < plan->pending.size() && take < (size_t)kServeBatchMax) {
-            BatchSize t = bs;  // copy
-            t.add(plan->pending[take].p, plan->pending[take].o);
-            if (t.total() > room) break;
-            bs = t;
-            ++take;
-        }
-        if (take == 0) break;  // the head waits for memory (FIFO: nothing overtakes it)
-        size_t off = 0;
-        (void)pool_take(plan, bs.total(), off);
-        std::vector<lqt_problem> ps(take);
-        std::vector<lqt_outputs> os(take);
-        std::vector<int32_t*> ovr(take);
-        for (size_t i = 0; i < take; ++i) {
-            ps[i] = plan->pending[i].p;
-            os[i] = plan->pending[i].o;
-            ovr[i] = s.status_dev + i;
-            s.tickets.push_back(plan->pending[i].ticket);
-        }
-        plan->pending.erase(plan->pending.begin(), plan->pending.begin() + take);
-        s.arena.ws = plan->pool + off;
-        s.arena.cap = bs.total();
-        s.off = off;
-        s.len = bs.total();
-        s.busy = true;
-        lqt_serve_stats& S = plan->stats;
-        S.batches += 1;
-        S.running_batches += 1;
-        S.max_running_batches = std::max(S.max_running_batches, S.running_batches);
-        S.max_batch = std::max(S.max_batch, (int32_t)take);
-        S.pool_in_use += s.len;
-        S.pool_peak = std::max(S.pool_peak, S.pool_in_use);
-        lqt_status st = solve_all(plan, s.arena, ps.data(), os.data(), (int32_t)take, s.stream, ovr.data());
-        if (st == LQT_OK &&
-            hipMemcpyAsync(s.status_host, s.status_dev, take * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream) !=
-                hipSuccess)
-            st = fail(plan, LQT_EHIP, "status copy failed");
-        for (size_t i = 0; st == LQT_OK && i < take; ++i)
-            if (os[i].status &&
-                hipMemcpyAsync(os[i].status, s.status_dev + i, sizeof(int32_t), hipMemcpyDefault, s.stream) !=
-                    hipSuccess)
-                st = fail(plan, LQT_EHIP, "status copy failed");
-        if (st == LQT_OK && hipEventRecord(s.done, s.stream) != hipSuccess)
-            st = fail(plan, LQT_EHIP, "event record failed");
-        if (st != LQT_OK) {
-            // part of the batch may be queued: wait for it before the range
-            // is reused, and report the launch failure for every request
-            (void)hipGetLastError();
-            (void)hipStreamSynchronize(s.stream);
-            (void)hipGetLastError();
-            slot_retire(plan, s, st);
-            return st;
-        }
-    }
+    plan->stop = false;
+    plan->progress = std::thread(serve_progress, plan);
     return LQT_OK;
 }
 
@@ -1290,47 +1261,54 @@ lqt_status lqt_submit(lqt_plan_t plan, const lqt_problem* prob, const lqt_output
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
     st = serve_init(plan);
     if (st != LQT_OK) return st;
+    (void)plan->core.pump(plan->ops);  // retire finished work first: it frees queue places
     const size_t need = serve_bytes(plan, *prob, *out);
-    if (need > plan->pool_size)
+    const uint64_t t = plan->next_ticket;
+    const int code = plan->core.submit(t, serve_lane(plan, *prob), need, (size_t)t);
+    if (code == LQT_ENOMEM)
         return fail(plan, LQT_ENOMEM, "lqt_submit: request needs %zu device bytes, the serving pool holds %zu", need,
-                    plan->pool_size);
-    st = serve_pump(plan);  // retire finished work first: it frees queue places
-    if (st != LQT_OK) return st;
-    if (plan->live >= (size_t)plan->desc.max_inflight)
-        return fail(plan, LQT_EBUSY, "lqt_submit: %zu requests queued or running (max %d)", plan->live,
+                    plan->core.pool().size());
+    if (code == LQT_EBUSY)
+        return fail(plan, LQT_EBUSY, "lqt_submit: %zu requests queued or running (max %d)", plan->core.live(),
                     plan->desc.max_inflight);
-    PendingReq r{plan->next_ticket++, *prob, *out};
-    plan->pending.push_back(r);
-    plan->state[r.ticket] = -1;
-    ++plan->live;
-    plan->stats.submitted += 1;
-    *ticket = r.ticket;
-    return serve_pump(plan);
+    plan->payload[t] = PendingReq{*prob, *out};
+    ++plan->next_ticket;
+    *ticket = t;
+    // a launch failure is the request's status (and that of its batch), read by lqt_poll
+    (void)plan->core.pump(plan->ops);
+    plan->wake.notify_all();
+    return LQT_OK;
 }
 
 lqt_status lqt_poll(lqt_plan_t plan, uint64_t ticket) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_poll: NULL plan");
     std::lock_guard<std::recursive_mutex> lk(plan->mu);
-    auto it = plan->state.find(ticket);
-    if (it == plan->state.end())
+    if (!plan->core.known(ticket))
         return fail(plan, LQT_EINVAL, "lqt_poll: unknown ticket %llu", (unsigned long long)ticket);
-    if (it->second < 0) {
+    if (plan->core.pending(ticket)) {
         if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-        lqt_status st = serve_pump(plan);
-        if (st != LQT_OK) return st;
-        it = plan->state.find(ticket);
-        if (it->second < 0) return LQT_EAGAIN;
+        (void)plan->core.pump(plan->ops);
     }
-    const int code = it->second;
-    plan->state.erase(it);
+    int code = 0;
+    if (!plan->core.poll(ticket, code)) return LQT_EAGAIN;
     return (lqt_status)code;
 }
 
 lqt_status lqt_serve_stats_read(lqt_plan_t plan, lqt_serve_stats* out) {
     if (!plan || !out) return fail(plan, LQT_EINVAL, "lqt_serve_stats_read: NULL argument");
     std::lock_guard<std::recursive_mutex> lk(plan->mu);
-    *out = plan->stats;
-    out->queued = (int32_t)plan->pending.size();
+    const lqt::ServeCounters& c = plan->core.counters();
+    *out = lqt_serve_stats{};
+    out->submitted = c.submitted;
+    out->completed = c.completed;
+    out->batches = c.batches;
+    out->queued = plan->core.queued();
+    out->running_batches = c.running_batches;
+    out->max_running_batches = c.max_running_batches;
+    out->max_batch = c.max_batch;
+    out->pool_bytes = plan->core.pool().size();
+    out->pool_in_use = plan->core.pool().in_use();
+    out->pool_peak = c.pool_peak;
     return LQT_OK;
 }
 
@@ -1472,6 +1450,14 @@ lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem* prob, const lqt_f
 
 lqt_status lqt_destroy(lqt_plan_t plan) {
     if (!plan) return LQT_OK;
+    if (plan->progress.joinable()) {
+        {
+            std::lock_guard<std::recursive_mutex> lk(plan->mu);
+            plan->stop = true;
+        }
+        plan->wake.notify_all();
+        plan->progress.join();
+    }
     (void)hipSetDevice(plan->desc.device);
     (void)hipDeviceSynchronize();
     for (Slot& s : plan->slots) slot_release(s);

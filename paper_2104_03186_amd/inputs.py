@@ -75,6 +75,23 @@ class LQTProblem:
         return self.T
 
 
+def prefix_problem(prob: LQTProblem, T: int) -> LQTProblem:
+    """The instance over its first T steps: per-step arrays cut to T, the
+    terminal data unchanged (what a device instance read as a prefix solves)."""
+    if not 1 <= T <= prob.T:
+        raise ValueError(f"T={T} outside 1..{prob.T}")
+    bits = {"F": PS_F, "c": PS_c, "L": PS_L, "H": PS_H, "X": PS_X, "U": PS_U, "M": PS_M}
+    kw = dataclasses.asdict(prob)
+    for f, bit in bits.items():
+        if kw[f] is not None and (prob.per_step & bit):
+            kw[f] = np.ascontiguousarray(kw[f][:T])
+    kw["r"] = np.ascontiguousarray(prob.r[:T])
+    if kw["s"] is not None:
+        kw["s"] = np.ascontiguousarray(prob.s[:T])
+    kw["T"] = T
+    return LQTProblem(**kw)
+
+
 def _rng(workload: int, instance: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, workload, instance])))
 

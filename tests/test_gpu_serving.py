@@ -209,3 +209,24 @@ def test_failure_isolated_in_batch(api):
     assert int(dos[1].status.item()) == 3
     for i in (0, 2, 3):
         check(dos[i].host(), oracle.solve(probs[i]))
+
+
+def test_progress_without_polling(api):
+    # the plan's progress thread launches queued requests and retires
+    # finished batches while the caller neither submits nor polls
+    probs = [served_request(8, 500 + 50 * i, 600 + i) for i in range(8)]
+    plan = api.Plan(32, 16, prec="mixed")
+    dps = [api.DeviceProblem(p) for p in probs]
+    dos = [out_for(api, p) for p in probs]
+    _say("progress without polling")
+    tickets = [plan.submit(dp, do) for dp, do in zip(dps, dos)]
+    t0 = time.time()
+    while plan.serve_stats()["completed"] < len(probs):
+        assert time.time() - t0 < 60, plan.serve_stats()
+        time.sleep(0.01)
+    st = plan.serve_stats()
+    assert st["running_batches"] == 0 and st["queued"] == 0 and st["pool_in_use"] == 0, st
+    assert wait_all(plan, tickets) == [0] * len(probs)
+    plan.close()
+    for p, do in zip(probs, dos):
+        check(do.host(), oracle.solve(p))

@@ -46,3 +46,14 @@ def test_serving_stream():
     reqs = inputs.serving_requests(rate_hz=2000.0, seconds=1.0)
     assert 1800 < len(reqs) < 2200
     assert all(4 <= n <= 32 and m == (n + 1) // 2 and 64 <= T <= 65536 for _, n, m, T in reqs)
+
+
+def test_prefix_problem_is_the_first_steps():
+    import oracle
+
+    full = inputs.random_problem(3, 2, 40, seed=4, per_step=1 | 2)
+    sub = inputs.prefix_problem(full, 25)
+    assert sub.T == 25 and sub.F.shape[0] == 25 and sub.r.shape[0] == 25
+    assert np.array_equal(sub.F, full.F[:25]) and np.array_equal(sub.rT, full.rT)
+    # its solution is that of a 25-step instance, not a slice of the 40-step one
+    assert oracle.solve(sub)["x"].shape == (26, 3)
