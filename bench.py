@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and FP64 matrix (dense)
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector and FP32 matrix (dense)
 
 # Measured HBM traffic per launch of the dominant kernel (rocprofv3 --pmc
 # FETCH_SIZE, then WRITE_SIZE, on `bench.py --workload single`), scaled by the
@@ -186,6 +187,7 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
     dom_launches, dom_ms = plan.profile_read()[dom_name]
     plan.profile(False)
     plan.profile_select(None)
+    per_solve = timing_stats(timed_solves(torch, stream, lambda: plan.solve([dp], [do], stream), 10))
     plan.close()
 
     ms_per_step = ms_total / steps
@@ -211,12 +213,13 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
         sps, secs, reps = oracle.time_solve([prob], min_seconds=args.cpu_seconds)
         cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} full sequential FP64 solve(s) of the same T={T} instance ({secs:.1f} s)"}
-    return {"value": value, "ms_per_step": ms_per_step, "status": status, "rel_err": rel_err,
+    return {"value": value, "ms_per_step": ms_per_step, "ms_per_solve_stats": per_solve, "status": status,
+            "rel_err": rel_err,
             "stages_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages_all.items()},
             "roofline": roofline, "path_roofline": path, "cpu_baseline": cpu, "wall_s": wall}
 
 
-def run_batched(args, api, inputs, torch, prec):
+def run_batched(args, api, inputs, torch, prec, with_cpu=False):
     """Uneven batch: 4096 instances, T log-uniform on [256, 16384], n in
     {4, 8, 16}, m = n / 2, diagonal costs, random-walk references; one
     lqt_solve call per step (all instances, every output family).  The
@@ -257,14 +260,28 @@ def run_batched(args, api, inputs, torch, prec):
     stages = plan.profile_read()
     plan.profile(False)
     times = timed_solves(torch, stream, lambda: plan.solve(dps, dos, stream), args.batched_steps)
+    # the same batch replayed from a recorded graph (lqt_set_graphs)
+    plan.set_graphs(True)
+    plan.solve(dps, dos, stream)
+    torch.cuda.synchronize()
+    st_graph = timing_stats(timed_solves(torch, stream, lambda: plan.solve(dps, dos, stream), args.batched_steps))
     plan.close()
     st = timing_stats(times)
     ms = st["mean"]
+    cpu = None
+    if with_cpu:
+        import oracle
+
+        sps, secs, used = oracle.time_solve_parallel(probs, oracle.host_threads())
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+               "sample": f"the whole batch ({count} instances, {steps_total} steps) over the host threads "
+                         f"({secs:.1f} s)"}
     return {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, m = n/2, T log-uniform "
                         f"[256, 16384], {prec}",
             "steps_per_solve": steps_total, "ms_per_solve": ms, "ms_per_solve_stats": st,
             "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s", "status_failures": status_bad,
-            "tuned_chunk_divisors": tuned,
+            "graph_replay_ms_per_solve_stats": st_graph,
+            "tuned_chunk_divisors": tuned, "cpu_baseline": cpu,
             "rel_err_sampled": rel_err,
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
 
@@ -274,7 +291,7 @@ def dense_flops_per_step(n, m):
     return path_flops_per_step(n, m)
 
 
-def run_dense(args, api, inputs, torch, prec):
+def run_dense(args, api, inputs, torch, prec, with_cpu=False):
     """Dense batch: 64 instances, n = 64, m = 32, T = 8192, dense SPD costs
     (Q = W W^T + 0.1 I), spectral radius 0.98, random-walk references."""
     probs = [inputs.dense_problem(64, 32, args.dense_T, instance=i) for i in range(args.dense_count)]
@@ -284,38 +301,48 @@ def run_dense(args, api, inputs, torch, prec):
     dps = [api.DeviceProblem(p) for p in probs]
     dos = [api.DeviceOutputs(p.n, p.m, p.T, dtype=dtype) for p in probs]
     stream = torch.cuda.current_stream(0)
-    plan.solve(dps, dos, stream)
+    for _ in range(args.batched_warmup):
+        plan.solve(dps, dos, stream)
     torch.cuda.synchronize()
     status_bad = sum(int(o.status.item()) != 0 for o in dos)
     rel_err = None
     if not args.no_parity:
         import oracle
 
-        ref = oracle.solve(probs[0])
-        got = dos[0].host()
-        rel_err = {f: rel(got[f], ref[f]) for f in api.FAMILIES}
+        worst = {f: 0.0 for f in api.FAMILIES}
+        for i in (0, len(probs) - 1):
+            ref = oracle.solve(probs[i])
+            got = dos[i].host()
+            for f in api.FAMILIES:
+                worst[f] = max(worst[f], rel(got[f], ref[f]))
+        rel_err = worst
     plan.profile(True)
     plan.profile_read()
     plan.solve(dps, dos, stream)
     stages = plan.profile_read()
     plan.profile(False)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.batched_steps):
-        plan.solve(dps, dos, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batched_steps
+    st = timing_stats(timed_solves(torch, stream, lambda: plan.solve(dps, dos, stream), args.batched_steps))
     plan.close()
+    ms = st["mean"]
     flops = dense_flops_per_step(64, 32) * steps_total
     tfs = flops / (ms / 1e3) / 1e12
+    cpu = None
+    if with_cpu:
+        import oracle
+
+        th = oracle.host_threads()
+        sample = probs[:th]
+        sps, secs, used = oracle.time_solve_parallel(sample, th)
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+               "sample": f"{len(sample)} of the {len(probs)} instances (T={args.dense_T}), one per host thread "
+                         f"({secs:.1f} s)"}
     return {"workload": f"dense batch {args.dense_count} x (n=64, m=32, T={args.dense_T}), {prec}",
-            "steps_per_solve": steps_total, "ms_per_solve": round(ms, 3),
+            "steps_per_solve": steps_total, "ms_per_solve": ms, "ms_per_solve_stats": st,
             "value": round(steps_total / (ms / 1e3), 1), "unit": "steps/s", "status_failures": status_bad,
-            "rel_err_instance0": rel_err, "algorithmic_tflops": round(tfs, 3),
-            "mfma_fp64_peak_frac": round(tfs / FP64_PEAK_TFLOPS, 4),
-            "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+            "rel_err_sampled": rel_err, "algorithmic_tflops": round(tfs, 3),
+            "algorithmic_fp64_peak_frac": round(tfs / FP64_PEAK_TFLOPS, 4),
+            "algorithmic_fp32_peak_frac": round(tfs / FP32_PEAK_TFLOPS, 4),
+            "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}, "cpu_baseline": cpu}
 
 
 def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
@@ -363,17 +390,19 @@ def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
     one()
     stages = plan.profile_read()
     plan.profile(False)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.nl_steps):
-        one()
-    e1.record(stream)
+    st_direct = timing_stats(timed_solves(torch, stream, one, args.nl_steps))
+    # the same solves replayed from a recorded graph (lqt_set_graphs)
+    plan.set_graphs(True)
+    one()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.nl_steps
+    st_graph = timing_stats(timed_solves(torch, stream, one, args.nl_steps))
+    recorded = plan.graphs_recorded()
     plan.close()
+    ms = st_direct["mean"]
     return {"workload": f"iterated nonlinear LQT, unicycle, T={T}, {rounds} rounds, {prec}",
-            "ms_per_solve": round(ms, 3), "ms_per_round": round(ms / rounds, 4),
+            "ms_per_solve": ms, "ms_per_round": round(ms / rounds, 4), "ms_per_solve_stats": st_direct,
+            "graph_replay": {"ms_per_solve_stats": st_graph, "ms_per_round": round(st_graph["mean"] / rounds, 4),
+                             "graphs_recorded": recorded},
             "value": round(T * rounds / (ms / 1e3), 1), "unit": "steps*rounds/s", "status": st,
             "rel_err": rel_err, "cpu_baseline": cpu,
             "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
@@ -488,7 +517,7 @@ def run_copy(args, torch):
             "ms_per_copy": round(ms, 4), "GBps_each_way": round(n * 8 / (ms / 1e3) / 1e9, 1)}
 
 
-def run_serving(args, api, inputs, torch, prec):
+def run_serving(args, api, inputs, torch, prec, with_cpu=False):
     """Poisson arrivals (args.rate req/s for args.serve_seconds s), nx ~ U{4..32},
     nu = ceil(nx / 2), T log-uniform on [64, 65536], diagonal costs and
     random-walk references; each request asks for K, d, x, u.  One instance
@@ -578,6 +607,16 @@ def run_serving(args, api, inputs, torch, prec):
     def pct(a, q):
         return round(float(np.percentile(np.asarray(a), q)), 3) if len(a) else None
 
+    cpu = None
+    if with_cpu:
+        import oracle
+
+        # the first requests of the stream, solved over the host threads
+        sample = [inputs.prefix_problem(inputs.diag_problem(n, m, Tmax, 4, n), T) for _, n, m, T in reqs[:256]]
+        sps, secs, used = oracle.time_solve_parallel(sample, oracle.host_threads())
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+               "sample": f"the first {len(sample)} requests of the stream over the host threads ({secs:.1f} s)"}
+
     return {"workload": f"serving: Poisson {args.rate:g} req/s for {args.serve_seconds:g} s, nx ~ U{{4..32}}, "
                         f"nu = ceil(nx/2), T log-uniform [64, 65536], {prec}, outputs K d x u",
             "requests": len(lat), "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
@@ -587,7 +626,7 @@ def run_serving(args, api, inputs, torch, prec):
             "alone_ms_by_shape": alone,
             "served_steps_per_s": round(served_steps / last_done, 1),
             "offered_steps_per_s": round(offered, 1), "elapsed_s": round(last_done, 3),
-            "serve_stats": stats, "rel_err_sampled": rel_err}
+            "serve_stats": stats, "rel_err_sampled": rel_err, "cpu_baseline": cpu}
 
 
 def main():
@@ -610,7 +649,7 @@ def main():
                          "reference s)")
     ap.add_argument("--nl-T", type=int, default=100_000)
     ap.add_argument("--nl-rounds", type=int, default=10)
-    ap.add_argument("--nl-steps", type=int, default=5)
+    ap.add_argument("--nl-steps", type=int, default=10)
     ap.add_argument("--block-steps", type=int, default=20)
     ap.add_argument("--fs-T", type=int, default=100_000)
     ap.add_argument("--fs-steps", type=int, default=20)
@@ -634,14 +673,15 @@ def main():
 
     from paper_2104_03186_amd import api, inputs
 
+    with_cpu = not args.no_cpu_baseline
     if args.workload == "batched":
-        print(json.dumps(run_batched(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        print(json.dumps(run_batched(args, api, inputs, torch, args.prec or "mixed", with_cpu)), flush=True)
         return
     if args.workload == "copy":
         print(json.dumps(run_copy(args, torch)), flush=True)
         return
     if args.workload == "dense":
-        print(json.dumps(run_dense(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        print(json.dumps(run_dense(args, api, inputs, torch, args.prec or "mixed", with_cpu)), flush=True)
         return
     if args.workload == "nonlinear":
         print(json.dumps(run_nonlinear(args, api, inputs, torch, args.prec or "fp64",
@@ -654,7 +694,7 @@ def main():
         print(json.dumps(run_finite(args, api, inputs, torch, not args.no_cpu_baseline)), flush=True)
         return
     if args.workload == "serving":
-        print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed")), flush=True)
+        print(json.dumps(run_serving(args, api, inputs, torch, args.prec or "mixed", with_cpu)), flush=True)
         return
     prec = args.prec or "fp64"
     main_res = run_single(args, api, inputs, torch, prec, args.steps, args.warmup, not args.no_cpu_baseline,
@@ -668,6 +708,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 4),
+        "ms_per_solve_stats": main_res["ms_per_solve_stats"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -686,7 +727,8 @@ def main():
     }
     if args.workload == "all":
         mixed = run_single(args, api, inputs, torch, "mixed", args.steps, args.warmup, False)
-        out["single_mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "status", "rel_err", "roofline")}
+        out["single_mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "ms_per_solve_stats", "status", "rel_err",
+                                                     "roofline")}
         m2 = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, trajectory="prefix")
         out["single_fp64_forward_prefixes"] = {k: m2[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                   "stages_avg_ms")}
@@ -696,9 +738,10 @@ def main():
         out["nonlinear_fp64"] = run_nonlinear(args, api, inputs, torch, "fp64", not args.no_cpu_baseline)
         out["finite_state"] = run_finite(args, api, inputs, torch, not args.no_cpu_baseline)
         out["block_sweep"] = run_blocks(args, api, inputs, torch)
-        out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed")
-        out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed")
-        out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed")
+        out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed", with_cpu)
+        out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed", with_cpu)
+        out["dense_fp64"] = run_dense(args, api, inputs, torch, "fp64")
+        out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed", with_cpu)
     print(json.dumps(out), flush=True)
 
 

@@ -214,6 +214,27 @@ lqt_status lqt_solve_noalloc(lqt_plan_t plan, const lqt_problem *prob, const lqt
 lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem *probs, const lqt_outputs *outs,
                     int32_t count, void *stream, int32_t *chosen);
 
+/* Graph replay of repeated calls (for callers that solve the same buffers
+ * again and again: a batch re-solved with new references, an iterated
+ * linearisation restarted from a new nominal).  With enable set, lqt_solve
+ * and lqt_nl_iterate record the launch sequence of a call the first time its
+ * signature is seen -- every argument's dimensions, per-step bits and device
+ * pointers, not the data -- as a HIP graph (stream capture on a stream of
+ * the plan), and replay that graph on the caller's stream for later calls
+ * with the same signature: one graph launch instead of every kernel launch
+ * and host-side preparation.  A replay performs the recorded work on the
+ * current contents of the same buffers, so its results equal those of a
+ * direct call bit for bit.  Each recorded signature owns its workspace:
+ * replays of one signature must be ordered by the caller like any work of
+ * the plan.  At most 64 signatures are kept (the set is cleared when full);
+ * lqt_set_routing, lqt_tune and disabling clear it.  While per-kernel timing
+ * is enabled calls run directly.  Off by default. */
+lqt_status lqt_set_graphs(lqt_plan_t plan, int32_t enable);
+
+/* Number of signatures currently recorded as graphs (negative lqt_status on
+ * error). */
+int32_t lqt_graphs_recorded(lqt_plan_t plan);
+
 /* Routing and chunking overrides of one plan (testing, tuning and the
  * block-length study of Section V-C).  They apply to the plan's later
  * lqt_solve, lqt_tune, lqt_submit and lqt_nl_iterate calls; other plans are

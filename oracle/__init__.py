@@ -173,6 +173,48 @@ def cost(prob, x: np.ndarray, u: np.ndarray) -> float:
                                  _p(x), _p(u)))
 
 
+def time_solve_parallel(probs, threads: int):
+    """Time the unmodified oracle over a list of problems on `threads` host
+    threads, the instances partitioned statically (longest first, each to the
+    least-loaded thread); one pass.  The C solve runs without the Python
+    interpreter lock, so the threads solve concurrently.  Returns
+    (steps_per_second, seconds, threads)."""
+    import threading
+
+    threads = max(1, min(threads, len(probs)))
+    cost = [int(p.n) ** 3 * int(p.T) + 1 for p in probs]
+    order = sorted(range(len(probs)), key=lambda i: -cost[i])
+    parts = [[] for _ in range(threads)]
+    load = [0] * threads
+    for i in order:
+        j = load.index(min(load))
+        parts[j].append(probs[i])
+        load[j] += cost[i]
+
+    def work(ps):
+        for p in ps:
+            solve(p)
+
+    ts = [threading.Thread(target=work, args=(ps,)) for ps in parts]
+    t0 = time.perf_counter()
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    el = time.perf_counter() - t0
+    return sum(int(p.T) for p in probs) / el, el, threads
+
+
+def host_threads(limit: int = 16) -> int:
+    """Host threads for a parallel baseline: the CPUs this process may use,
+    at most `limit`."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(limit, n))
+
+
 def time_solve(probs, min_seconds: float = 10.0, max_reps: int = 1000):
     """Time the unmodified oracle on one host core over a list of problems.
 

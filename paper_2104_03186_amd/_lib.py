@@ -22,7 +22,7 @@ PS_F, PS_c, PS_L, PS_H, PS_X, PS_U = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("lqt_plan", "lqt_solve", "lqt_tune", "lqt_submit", "lqt_poll", "lqt_serve_stats_read", "lqt_destroy",
             "lqt_profile_enable", "lqt_profile_select", "lqt_profile_read", "lqt_last_error", "lqt_nl_iterate",
-            "lqt_fs_solve", "lqt_set_routing", "lqt_solve_noalloc")
+            "lqt_fs_solve", "lqt_set_routing", "lqt_solve_noalloc", "lqt_set_graphs", "lqt_graphs_recorded")
 
 _vp = ctypes.c_void_p
 
@@ -126,6 +126,10 @@ def load() -> ctypes.CDLL:
     lib.lqt_nl_iterate.restype = ctypes.c_int
     lib.lqt_fs_solve.argtypes = [_vp, ctypes.POINTER(FSProblem), ctypes.POINTER(FSOutputs), _vp]
     lib.lqt_fs_solve.restype = ctypes.c_int
+    lib.lqt_graphs_recorded.argtypes = [_vp]
+    lib.lqt_graphs_recorded.restype = ctypes.c_int32
+    lib.lqt_set_graphs.argtypes = [_vp, ctypes.c_int32]
+    lib.lqt_set_graphs.restype = ctypes.c_int
     lib.lqt_set_routing.argtypes = [_vp, ctypes.POINTER(Routing)]
     lib.lqt_set_routing.restype = ctypes.c_int
     lib.lqt_last_error.argtypes = [_vp]

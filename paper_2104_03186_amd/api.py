@@ -201,6 +201,18 @@ class Plan:
         _lib.check(_lib.load().lqt_tune(self._h, P, O, n, ctypes.c_void_p(stream.cuda_stream), ch), self._h)
         return list(ch)
 
+    def set_graphs(self, enable: bool = True) -> None:
+        """Record repeated solve / nl_iterate calls as HIP graphs and replay
+        them (lqt_set_graphs)."""
+        _lib.check(_lib.load().lqt_set_graphs(self._h, 1 if enable else 0), self._h)
+
+    def graphs_recorded(self) -> int:
+        """Signatures currently recorded as graphs (lqt_graphs_recorded)."""
+        n = _lib.load().lqt_graphs_recorded(self._h)
+        if n < 0:
+            raise _lib.LQTError(-n, _lib.last_error(self._h))
+        return n
+
     def set_routing(self, path: Optional[str] = None, wave_engine_only: bool = False, lane_chunk: int = 0,
                     wave_chunk: int = 0) -> None:
         """Routing and chunking overrides of this plan (lqt_set_routing):

@@ -159,6 +159,14 @@ struct Arena {
     lqt::SmallArgs* sargs_host = nullptr;  // batched-lane instance table (pinned)
     size_t sargs_cap = 0;
     hipEvent_t ginst_done = nullptr;       // both tables uploaded
+    bool capture = false;  // work is being recorded into a graph: no host waits on events, none recorded
+};
+
+// A recorded launch sequence of the plan (lqt_set_graphs): the graph and the
+// arenas it runs in, which no other work of the plan uses.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    Arena main, nl;
 };
 
 // Device side of one serving slot: its stream, its batch's arena (a range of
@@ -204,6 +212,10 @@ struct lqt_plan_s {
     std::thread progress;
     std::condition_variable_any wake;
     bool stop = false;
+    // graph replay (lqt_set_graphs): recorded launch sequences by call signature
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, GraphEntry*> gcache;
     int tune_div[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // chunks per instance per launch group (0: default)
     lqt_routing route{};                          // routing and chunking overrides (lqt_set_routing)
     lqt::SideStream side{};  // prefix trajectory: element scan beside the backward pass
@@ -668,7 +680,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         st = launch_one(plan, base, probs[i], outs[i], s, status_override ? status_override[i] : nullptr, f32);
         if (st != LQT_OK) return st;
     }
-    if ((!batch.empty() || !wave.empty()) && A.ginst_done)
+    if ((!batch.empty() || !wave.empty()) && A.ginst_done && !A.capture)
         (void)hipEventSynchronize(A.ginst_done);  // the previous upload has left the host tables
     if (!batch.empty()) {
         // one launch pair per (n, m, step-data mode) group
@@ -709,7 +721,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
             if (e != hipSuccess) return fail(plan, LQT_EHIP, "batched lane launch failed: %s", hipGetErrorString(e));
             j0 = j1;
         }
-        if (wave.empty()) {
+        if (wave.empty() && !A.capture) {
             if (!A.ginst_done && hipEventCreateWithFlags(&A.ginst_done, hipEventDisableTiming) != hipSuccess)
                 return fail(plan, LQT_EHIP, "event creation failed");
             (void)hipEventRecord(A.ginst_done, s);
@@ -742,9 +754,11 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     if (hipMemcpyAsync(d_inst, A.ginst_host, wave.size() * sizeof(lqt::GInst), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return fail(plan, LQT_EHIP, "instance table upload failed");
-    if (!A.ginst_done && hipEventCreateWithFlags(&A.ginst_done, hipEventDisableTiming) != hipSuccess)
-        return fail(plan, LQT_EHIP, "event creation failed");
-    (void)hipEventRecord(A.ginst_done, s);
+    if (!A.capture) {
+        if (!A.ginst_done && hipEventCreateWithFlags(&A.ginst_done, hipEventDisableTiming) != hipSuccess)
+            return fail(plan, LQT_EHIP, "event creation failed");
+        (void)hipEventRecord(A.ginst_done, s);
+    }
     lqt::StageHook hook{&Profiler::begin, &Profiler::end, &plan->prof};
     // chunked groups of a plan with forward prefixes and float results run
     // with double results (wide) and are rounded afterwards
@@ -1065,6 +1079,162 @@ lqt_status serve_init(lqt_plan_t plan) {
     return LQT_OK;
 }
 
+// The rounds of lqt_nl_iterate enqueued on stream s, with the linearised
+// model in arena NA and the solves in arena MA (p, o: the validated instance
+// of a round, model pointers filled in here).
+lqt_status nl_enqueue(lqt_plan_t plan, Arena& NA, Arena& MA, const lqt_nl_problem& pr, lqt_problem p, lqt_outputs o,
+                      int32_t iterations, void* x, void* u, double* change, int32_t* status, hipStream_t s) {
+    const lqt_nl_problem* prob = &pr;
+    const int n = 4, m = 2;
+    const int64_t T = prob->T;
+    lqt_status st = LQT_OK;
+    // A MIXED plan iterates in double: the nominal trajectory of every round
+    // is kept in double workspace (xd, ud), each round is solved with double
+    // results, and only the last round's x and u are rounded to float.
+    const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
+    const size_t model = align_up((size_t)T * (n * n + n * m + n + m) * sizeof(double));
+    const size_t nominal = f32 ? align_up((size_t)((T + 1) * n + T * m) * sizeof(double)) : 0;
+    st = ensure_ws(plan, NA, model + nominal + align_up((size_t)iterations * sizeof(int32_t)));
+    if (st != LQT_OK) return st;
+    lqt::NlArgs g{};
+    g.dt = prob->dt;
+    g.T = T;
+    g.F = (double*)NA.ws;
+    g.L = g.F + (size_t)T * n * n;
+    g.c = g.L + (size_t)T * n * m;
+    g.ubar = g.c + (size_t)T * n;
+    double* xd = f32 ? (double*)(NA.ws + model) : nullptr;
+    double* ud = f32 ? xd + (size_t)(T + 1) * n : nullptr;
+    g.x = f32 ? xd : (const double*)x;
+    g.u = f32 ? ud : (const double*)u;
+    int32_t* round_status = (int32_t*)(NA.ws + model + nominal);
+    p.F = g.F; p.L = g.L; p.c = g.c;
+    o.x = f32 ? (void*)xd : x;
+    o.u = f32 ? (void*)ud : u;
+    auto launched = [&](hipError_t e) -> lqt_status {
+        return e == hipSuccess ? LQT_OK : fail(plan, LQT_EHIP, "launch failed: %s", hipGetErrorString(e));
+    };
+    if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
+    if (f32) {
+        if ((st = launched(lqt::convert_array(x, true, xd, false, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(u, true, ud, false, T * m, s))) != LQT_OK) return st;
+    }
+    for (int it = 0; it < iterations; ++it) {
+        // the change of round it - 1 is completed by this round's linearisation
+        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_linearise", s);
+        st = launched(lqt::nl_linearise(g, (change && it > 0) ? change + it - 1 : nullptr, s));
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        if (st != LQT_OK) return st;
+        o.status = round_status + it;
+        if ((st = solve_all(plan, MA, &p, &o, 1, s, nullptr, 0)) != LQT_OK) return st;
+    }
+    if (change) {
+        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
+        st = launched(lqt::nl_change(g, change + iterations - 1, s));
+        if (plan->prof.on) Profiler::end(&plan->prof, s);
+        if (st != LQT_OK) return st;
+    }
+    if (f32) {
+        if ((st = launched(lqt::convert_array(xd, false, x, true, (T + 1) * n, s))) != LQT_OK) return st;
+        if ((st = launched(lqt::convert_array(ud, false, u, true, T * m, s))) != LQT_OK) return st;
+    }
+    return launched(lqt::nl_finish(round_status, iterations, status, s));
+}
+
+
+// ---- graph replay (lqt_set_graphs) ------------------------------------------
+//
+// A call whose signature (every argument's bytes: dimensions, per-step bits
+// and device pointers) has been seen before replays the HIP graph recorded
+// for it.  The first call runs directly in the entry's own arenas (sizing
+// them, producing its results), then the same enqueue is recorded by stream
+// capture on the plan's capture stream and instantiated.  Every host-side
+// decision of an enqueue depends on the signature alone, and the instance
+// tables of a graph live in its own pinned buffers, so a replay performs the
+// recorded work on the current contents of the same buffers.
+
+void sig_add(std::string& k, const void* p, size_t n) { k.append((const char*)p, n); }
+
+template <class T>
+void sig_val(std::string& k, const T& v) {
+    sig_add(k, &v, sizeof v);
+}
+
+// field by field (struct padding is not part of a signature)
+void sig_problem(std::string& k, const lqt_problem& p) {
+    sig_val(k, p.nx); sig_val(k, p.nu); sig_val(k, p.ny); sig_val(k, p.nyT); sig_val(k, p.T);
+    sig_val(k, p.per_step);
+    const double* ptr[] = {p.F, p.c, p.L, p.H, p.X, p.U, p.r, p.HT, p.XT, p.rT, p.x0, p.M, p.s};
+    sig_add(k, ptr, sizeof ptr);
+}
+
+void sig_outputs(std::string& k, const lqt_outputs& o) {
+    const void* ptr[] = {o.S, o.v, o.K, o.d, o.x, o.u, o.status};
+    sig_add(k, ptr, sizeof ptr);
+}
+
+void sig_nl(std::string& k, const lqt_nl_problem& p) {
+    sig_val(k, (int32_t)p.model); sig_val(k, p.ny); sig_val(k, p.nyT); sig_val(k, p.T); sig_val(k, p.per_step);
+    const double* ptr[] = {p.dt, p.H, p.X, p.U, p.r, p.HT, p.XT, p.rT, p.x0};
+    sig_add(k, ptr, sizeof ptr);
+}
+
+constexpr size_t kGraphCacheMax = 64;  // recorded signatures kept per plan
+
+void graph_free(GraphEntry* e) {
+    if (!e) return;
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    arena_release(e->main);
+    arena_release(e->nl);
+    delete e;
+}
+
+void graph_clear(lqt_plan_t plan) {
+    if (plan->gcache.empty()) return;
+    (void)hipDeviceSynchronize();  // a replay in flight may still use an entry's arenas
+    for (auto& kv : plan->gcache) graph_free(kv.second);
+    plan->gcache.clear();
+}
+
+template <class Enqueue>
+lqt_status graph_run(lqt_plan_t plan, const std::string& key, hipStream_t s, Enqueue enqueue) {
+    auto it = plan->gcache.find(key);
+    if (it != plan->gcache.end()) {
+        if (hipGraphLaunch(it->second->exec, s) != hipSuccess)
+            return fail(plan, LQT_EHIP, "graph launch failed: %s", hipGetErrorString(hipGetLastError()));
+        return LQT_OK;
+    }
+    if (plan->gcache.size() >= kGraphCacheMax) graph_clear(plan);
+    GraphEntry* e = new (std::nothrow) GraphEntry();
+    if (!e) return fail(plan, LQT_ENOMEM, "graph entry: out of host memory");
+    lqt_status st = enqueue(*e, s);  // direct run: sizes the arenas, produces this call's results
+    if (st != LQT_OK) {
+        (void)hipStreamSynchronize(s);
+        graph_free(e);
+        return st;
+    }
+    for (Arena* A : {&e->main, &e->nl})
+        if (A->ginst_done) (void)hipEventSynchronize(A->ginst_done);  // host tables free to be rewritten
+    e->main.capture = e->nl.capture = true;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+        const lqt_status cst = enqueue(*e, plan->cap_stream);
+        ok = hipStreamEndCapture(plan->cap_stream, &g) == hipSuccess && cst == LQT_OK && g;
+    }
+    e->main.capture = e->nl.capture = false;
+    if (ok) ok = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ok) {  // not recorded: this call's results stand, later calls record again
+        (void)hipStreamSynchronize(s);
+        graph_free(e);
+        return LQT_OK;
+    }
+    plan->gcache[key] = e;
+    return LQT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1163,7 +1333,17 @@ lqt_status lqt_solve(lqt_plan_t plan, const lqt_problem* probs, const lqt_output
     }
     if (count == 0) return LQT_OK;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-    return solve_all(plan, plan->main, probs, outs, count, (hipStream_t)stream, nullptr);
+    hipStream_t s = (hipStream_t)stream;
+    if (!plan->graphs || plan->prof.on) return solve_all(plan, plan->main, probs, outs, count, s, nullptr);
+    std::string key("solve");
+    sig_val(key, count);
+    for (int32_t i = 0; i < count; ++i) {
+        sig_problem(key, probs[i]);
+        sig_outputs(key, outs[i]);
+    }
+    return graph_run(plan, key, s, [&](GraphEntry& e, hipStream_t gs) {
+        return solve_all(plan, e.main, probs, outs, count, gs, nullptr);
+    });
 }
 
 lqt_status lqt_solve_noalloc(lqt_plan_t plan, const lqt_problem* prob, const lqt_outputs* out, void* stream) {
@@ -1193,6 +1373,7 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
     }
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
+    graph_clear(plan);  // recorded launch sequences follow the chunk lengths
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(plan, LQT_EHIP, "lqt_tune: event creation failed");
@@ -1234,10 +1415,35 @@ lqt_status lqt_tune(lqt_plan_t plan, const lqt_problem* probs, const lqt_outputs
     return st;
 }
 
+lqt_status lqt_set_graphs(lqt_plan_t plan, int32_t enable) {
+    if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_set_graphs: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    plan->err.clear();
+    if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
+    if (!enable) {
+        graph_clear(plan);
+        plan->graphs = false;
+        return LQT_OK;
+    }
+    if (!plan->cap_stream && hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(plan, LQT_EHIP, "lqt_set_graphs: capture stream creation failed");
+    }
+    plan->graphs = true;
+    return LQT_OK;
+}
+
+int32_t lqt_graphs_recorded(lqt_plan_t plan) {
+    if (!plan) return -(int32_t)fail(nullptr, LQT_EINVAL, "lqt_graphs_recorded: NULL plan");
+    std::lock_guard<std::recursive_mutex> lk(plan->mu);
+    return (int32_t)plan->gcache.size();
+}
+
 lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing* routing) {
     if (!plan) return fail(nullptr, LQT_EINVAL, "lqt_set_routing: NULL plan");
     std::lock_guard<std::recursive_mutex> lk(plan->mu);
     plan->err.clear();
+    graph_clear(plan);  // recorded launch sequences follow the routing
     if (!routing) {
         plan->route = lqt_routing{};
         return LQT_OK;
@@ -1342,58 +1548,17 @@ lqt_status lqt_nl_iterate(lqt_plan_t plan, const lqt_nl_problem* prob, int32_t i
     lqt_status st = validate(plan, p, o, 0);
     if (st != LQT_OK) return st;
     if (hipSetDevice(plan->desc.device) != hipSuccess) return fail(plan, LQT_EHIP, "hipSetDevice failed");
-    // A MIXED plan iterates in double: the nominal trajectory of every round
-    // is kept in double workspace (xd, ud), each round is solved with double
-    // results, and only the last round's x and u are rounded to float.
-    const bool f32 = plan->desc.prec == LQT_PREC_MIXED;
-    const size_t model = align_up((size_t)T * (n * n + n * m + n + m) * sizeof(double));
-    const size_t nominal = f32 ? align_up((size_t)((T + 1) * n + T * m) * sizeof(double)) : 0;
-    st = ensure_ws(plan, plan->nl, model + nominal + align_up((size_t)iterations * sizeof(int32_t)));
-    if (st != LQT_OK) return st;
-    lqt::NlArgs g{};
-    g.dt = prob->dt;
-    g.T = T;
-    g.F = (double*)plan->nl.ws;
-    g.L = g.F + (size_t)T * n * n;
-    g.c = g.L + (size_t)T * n * m;
-    g.ubar = g.c + (size_t)T * n;
-    double* xd = f32 ? (double*)(plan->nl.ws + model) : nullptr;
-    double* ud = f32 ? xd + (size_t)(T + 1) * n : nullptr;
-    g.x = f32 ? xd : (const double*)x;
-    g.u = f32 ? ud : (const double*)u;
-    int32_t* round_status = (int32_t*)(plan->nl.ws + model + nominal);
-    p.F = g.F; p.L = g.L; p.c = g.c;
-    o.x = f32 ? (void*)xd : x;
-    o.u = f32 ? (void*)ud : u;
     hipStream_t s = (hipStream_t)stream;
-    auto launched = [&](hipError_t e) -> lqt_status {
-        return e == hipSuccess ? LQT_OK : fail(plan, LQT_EHIP, "launch failed: %s", hipGetErrorString(e));
-    };
-    if ((st = launched(lqt::nl_start(change, iterations, round_status, s))) != LQT_OK) return st;
-    if (f32) {
-        if ((st = launched(lqt::convert_array(x, true, xd, false, (T + 1) * n, s))) != LQT_OK) return st;
-        if ((st = launched(lqt::convert_array(u, true, ud, false, T * m, s))) != LQT_OK) return st;
-    }
-    for (int it = 0; it < iterations; ++it) {
-        // the change of round it - 1 is completed by this round's linearisation
-        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_linearise", s);
-        st = launched(lqt::nl_linearise(g, (change && it > 0) ? change + it - 1 : nullptr, s));
-        if (plan->prof.on) Profiler::end(&plan->prof, s);
-        if (st != LQT_OK) return st;
-        o.status = round_status + it;
-        if ((st = solve_all(plan, plan->main, &p, &o, 1, s, nullptr, 0)) != LQT_OK) return st;
-    }
-    if (change) {
-        if (plan->prof.on) Profiler::begin(&plan->prof, "nl_change", s);
-        st = launched(lqt::nl_change(g, change + iterations - 1, s));
-        if (plan->prof.on) Profiler::end(&plan->prof, s);
-        if (st != LQT_OK) return st;
-    }
-    if (f32) {
-        if ((st = launched(lqt::convert_array(xd, false, x, true, (T + 1) * n, s))) != LQT_OK) return st;
-        if ((st = launched(lqt::convert_array(ud, false, u, true, T * m, s))) != LQT_OK) return st;
-    }
-    return launched(lqt::nl_finish(round_status, iterations, status, s));
+    if (!plan->graphs || plan->prof.on) return nl_enqueue(plan, plan->nl, plan->main, *prob, p, o, iterations, x, u,
+                                                          change, status, s);
+    std::string key("nl");
+    sig_nl(key, *prob);
+    sig_val(key, iterations);
+    void* ptrs[4] = {x, u, change, status};
+    sig_add(key, ptrs, sizeof ptrs);
+    return graph_run(plan, key, s, [&](GraphEntry& e, hipStream_t gs) {
+        return nl_enqueue(plan, e.nl, e.main, *prob, p, o, iterations, x, u, change, status, gs);
+    });
 }
 
 lqt_status lqt_fs_solve(lqt_plan_t plan, const lqt_fs_problem* prob, const lqt_fs_outputs* out, void* stream) {
@@ -1460,6 +1625,8 @@ lqt_status lqt_destroy(lqt_plan_t plan) {
     }
     (void)hipSetDevice(plan->desc.device);
     (void)hipDeviceSynchronize();
+    graph_clear(plan);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     for (Slot& s : plan->slots) slot_release(s);
     if (plan->pool) (void)hipFree(plan->pool);
     if (plan->has_side) {
