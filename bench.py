@@ -116,6 +116,25 @@ def rel(a, b):
     return max(stacked, step)
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}; {os.cpu_count()} logical CPUs visible"
+
+
+def note(msg):
+    """A progress line on stderr (the JSON result stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timing_stats(ms_list):
     a = np.asarray(ms_list, dtype=np.float64)
     return {"mean": round(float(a.mean()), 4), "median": round(float(np.median(a)), 4),
@@ -211,7 +230,7 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
         import oracle
 
         sps, secs, reps = oracle.time_solve([prob], min_seconds=args.cpu_seconds)
-        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"{reps} full sequential FP64 solve(s) of the same T={T} instance ({secs:.1f} s)"}
     return {"value": value, "ms_per_step": ms_per_step, "ms_per_solve_stats": per_solve, "status": status,
             "rel_err": rel_err,
@@ -273,7 +292,7 @@ def run_batched(args, api, inputs, torch, prec, with_cpu=False):
         import oracle
 
         sps, secs, used = oracle.time_solve_parallel(probs, oracle.host_threads())
-        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle", "host": host_cpu(),
                "sample": f"the whole batch ({count} instances, {steps_total} steps) over the host threads "
                          f"({secs:.1f} s)"}
     return {"workload": f"batched {count} uneven instances, n in {{4,8,16}}, m = n/2, T log-uniform "
@@ -333,7 +352,7 @@ def run_dense(args, api, inputs, torch, prec, with_cpu=False):
         th = oracle.host_threads()
         sample = probs[:th]
         sps, secs, used = oracle.time_solve_parallel(sample, th)
-        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle", "host": host_cpu(),
                "sample": f"{len(sample)} of the {len(probs)} instances (T={args.dense_T}), one per host thread "
                          f"({secs:.1f} s)"}
     return {"workload": f"dense batch {args.dense_count} x (n=64, m=32, T={args.dense_T}), {prec}",
@@ -383,7 +402,7 @@ def run_nonlinear(args, api, inputs, torch, prec, with_cpu=True):
             rel_err = {"x": rel(x.double().cpu().numpy(), rx), "u": rel(u.double().cpu().numpy(), ru),
                        "last_change_gpu": float(change[-1].item()), "last_change_oracle": rch[-1]}
         if with_cpu:
-            cpu = {"value": round(T * rounds / secs, 1), "unit": "steps*rounds/s", "cores": 1, "kind": "oracle",
+            cpu = {"value": round(T * rounds / secs, 1), "unit": "steps*rounds/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
                    "sample": f"one full sequential FP64 iteration ({rounds} rounds, T={T}; {secs:.1f} s)"}
     plan.profile(True)
     plan.profile_read()
@@ -438,7 +457,7 @@ def run_finite(args, api, inputs, torch, with_cpu=True):
                 got = do.host()
                 exact = all(np.array_equal(got[f], ref[f]) for f in got)
             if with_cpu:
-                cpu = {"value": round(T / secs, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+                cpu = {"value": round(T / secs, 1), "unit": "steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
                        "sample": f"one full sequential solve (T={T}; {secs:.2f} s)"}
         plan.profile(True)
         plan.profile_read()
@@ -496,6 +515,88 @@ def run_blocks(args, api, inputs, torch):
     best = min(res, key=res.get)
     return {"workload": f"block length sweep, tracking n=4 m=2 T={T} fp64", "ms_per_solve_by_block": res,
             "best_block": int(best)}
+
+
+def condensed_problem(prob, B):
+    """Partial condensing (Section V-C) of a time-invariant instance with block
+    length B: the LQT over the block boundaries x_{jB}, j = 0..T/B, whose
+    control is the block's B controls stacked (dimension B m) and whose stage
+    cost is the block's B stage costs written in (x_{jB}, U_j).  With the
+    outputs of the block stacked, Y = H_B x + G_B U + h, H_B = [H F^i]_i,
+    G_B[i][l] = H F^(i-1-l) L (l < i), h_i = H sum_{l<i} F^(i-1-l) c, the
+    cost is the generalised stage cost of Section IV-D with H' = H_B,
+    r' = r_B - h, X' = blockdiag(X), M' = X' G_B, U' = G_B^T X' G_B +
+    blockdiag(U), s' = 0; the dynamics are F' = F^B, L' = [F^(B-1-l) L]_l,
+    c' = sum_l F^(B-1-l) c.  Host-side set-up of the condensing experiment
+    (the library does not condense)."""
+    import dataclasses
+
+    from paper_2104_03186_amd import inputs as _inputs
+
+    n, m, p, T = prob.n, prob.m, prob.p, prob.T
+    if prob.per_step or prob.M is not None or prob.s is not None or T % B:
+        raise ValueError("condensing needs a time-invariant standard-cost instance with B dividing T")
+    F, L, H, X, U = prob.F, prob.L, prob.H, prob.X, prob.U
+    c = np.zeros(n) if prob.c is None else np.asarray(prob.c, dtype=np.float64)
+    Fp = [np.eye(n)]
+    for _ in range(B):
+        Fp.append(Fp[-1] @ F)
+    HB = np.concatenate([H @ Fp[i] for i in range(B)], axis=0)
+    GB = np.zeros((B * p, B * m))
+    h = np.zeros(B * p)
+    for i in range(B):
+        for l in range(i):
+            GB[i * p:(i + 1) * p, l * m:(l + 1) * m] = H @ Fp[i - 1 - l] @ L
+        h[i * p:(i + 1) * p] = H @ sum((Fp[i - 1 - l] @ c for l in range(i)), np.zeros(n))
+    XB = np.kron(np.eye(B), X)
+    UB = np.kron(np.eye(B), U)
+    Fc = Fp[B]
+    Lc = np.concatenate([Fp[B - 1 - l] @ L for l in range(B)], axis=1)
+    cc = sum((Fp[B - 1 - l] @ c for l in range(B)), np.zeros(n))
+    rB = np.ascontiguousarray(prob.r.reshape(T // B, B * p) - h[None, :])
+    Mc = XB @ GB
+    Uc = GB.T @ XB @ GB + UB
+    Uc = 0.5 * (Uc + Uc.T)
+    return _inputs.LQTProblem(n=n, m=B * m, p=B * p, pT=prob.pT, T=T // B, per_step=0, F=Fc,
+                              c=None if prob.c is None else cc, L=Lc, H=HB, X=XB, U=Uc, r=rB,
+                              HT=prob.HT, XT=prob.XT, rT=prob.rT, x0=prob.x0, M=Mc,
+                              s=np.zeros((T // B, B * m)))
+
+
+def run_condensing(args, api, inputs, torch):
+    """Partial condensing against the block fold (Section V-C): the headline
+    tracking instance (n = 4, m = 2, T = args.T, FP64) condensed with block
+    length B into T / B steps of B m controls and B n outputs, solved through
+    the generalised-cost path (S, v, K, d, x, u of the condensed LQT), beside
+    the direct solve, whose lanes fold blocks of B steps themselves.  The
+    condensed instance's set-up (host) is outside the timed region."""
+    n, m, T = 4, 2, args.T
+    prob = inputs.tracking_problem(n=n, m=m, T=T, workload=1)
+    stream = torch.cuda.current_stream(0)
+    res = {}
+    for B in (2, 4, 8, 16):
+        cp = condensed_problem(prob, B)
+        plan = api.Plan(cp.n, cp.m, prec="fp64", device=0, max_steps=cp.T)
+        try:
+            dp = api.DeviceProblem(cp)
+            do = api.DeviceOutputs(cp.n, cp.m, cp.T)
+            for _ in range(2):
+                plan.solve([dp], [do], stream)
+            torch.cuda.synchronize()
+            st = int(do.status.item())
+            plan.profile(True)
+            plan.profile_read()
+            plan.solve([dp], [do], stream)
+            stages = plan.profile_read()
+            plan.profile(False)
+            times = timing_stats(timed_solves(torch, stream, lambda: plan.solve([dp], [do], stream),
+                                              args.block_steps))
+        finally:
+            plan.close()
+        res[str(B)] = {"condensed_steps": cp.T, "controls": cp.m, "outputs": cp.p, "status": st,
+                       "ms_per_solve_stats": times,
+                       "stage_ms_one_solve": {k: round(v[1], 4) for k, v in stages.items()}}
+    return {"workload": f"partial condensing, tracking n=4 m=2 T={T} fp64, block length B", "by_block": res}
 
 
 def run_copy(args, torch):
@@ -614,7 +715,7 @@ def run_serving(args, api, inputs, torch, prec, with_cpu=False):
         # the first requests of the stream, solved over the host threads
         sample = [inputs.prefix_problem(inputs.diag_problem(n, m, Tmax, 4, n), T) for _, n, m, T in reqs[:256]]
         sps, secs, used = oracle.time_solve_parallel(sample, oracle.host_threads())
-        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle",
+        cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": used, "kind": "oracle", "host": host_cpu(),
                "sample": f"the first {len(sample)} requests of the stream over the host threads ({secs:.1f} s)"}
 
     return {"workload": f"serving: Poisson {args.rate:g} req/s for {args.serve_seconds:g} s, nx ~ U{{4..32}}, "
@@ -639,7 +740,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "nonlinear", "finite",
-                                           "blocks", "copy"), default="all")
+                                           "blocks", "condensing", "copy"), default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
@@ -690,6 +791,9 @@ def main():
     if args.workload == "blocks":
         print(json.dumps(run_blocks(args, api, inputs, torch)), flush=True)
         return
+    if args.workload == "condensing":
+        print(json.dumps(run_condensing(args, api, inputs, torch)), flush=True)
+        return
     if args.workload == "finite":
         print(json.dumps(run_finite(args, api, inputs, torch, not args.no_cpu_baseline)), flush=True)
         return
@@ -725,23 +829,34 @@ def main():
         "path_roofline": main_res["path_roofline"],
         "cpu_baseline": main_res["cpu_baseline"],
     }
+    note(f"single fp64 T={args.T}: {main_res['ms_per_step']:.4f} ms per solve")
     if args.workload == "all":
         mixed = run_single(args, api, inputs, torch, "mixed", args.steps, args.warmup, False)
         out["single_mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "ms_per_solve_stats", "status", "rel_err",
                                                      "roofline")}
+        note("single mixed done")
         m2 = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, trajectory="prefix")
         out["single_fp64_forward_prefixes"] = {k: m2[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                   "stages_avg_ms")}
+        note("single forward prefixes done")
         gen = run_single(args, api, inputs, torch, "fp64", max(10, args.steps // 2), 2, False, cost="generalised")
         out["single_fp64_generalised_cost"] = {k: gen[k] for k in ("value", "ms_per_step", "status", "rel_err",
                                                                    "stages_avg_ms")}
+        note("single generalised cost done")
         out["nonlinear_fp64"] = run_nonlinear(args, api, inputs, torch, "fp64", not args.no_cpu_baseline)
+        note("nonlinear done")
         out["finite_state"] = run_finite(args, api, inputs, torch, not args.no_cpu_baseline)
+        note("finite state done")
         out["block_sweep"] = run_blocks(args, api, inputs, torch)
+        note("block sweep done")
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed", with_cpu)
+        note("batched done")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed", with_cpu)
+        note("dense mixed done")
         out["dense_fp64"] = run_dense(args, api, inputs, torch, "fp64")
+        note("dense fp64 done")
         out["serving_mixed"] = run_serving(args, api, inputs, torch, "mixed", with_cpu)
+        note("serving done")
     print(json.dumps(out), flush=True)
 
 
