@@ -38,12 +38,12 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector and FP32 matrix (dense)
 # plain-copy calibration (`bench.py --workload copy`: FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Reported only while the kernel sources hash to the
 # version the counters were taken on.
-TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
+TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_lane.hpp", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
 TRAFFIC = {
     ("bwd_final", "fp64", 1_000_000): {
-        "bytes_per_launch": 309_586_330,
-        "fetch_kib": 26486.5, "write_kib": 249357.4, "fetch_scale": 2.0, "write_scale": 1.0,
-        "src_sha256": "149f80ad099b208d26e1edf052a91d11c8f66566c9e014001ea6cb6b6c8d4daf",
+        "bytes_per_launch": 310_378_720,
+        "fetch_kib": 26487.2, "write_kib": 250129.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "src_sha256": "f3062b7ba5dd28357077d134e106c390e8e753bc92a4c0920ab11597f5481a0b",
     },
 }
 

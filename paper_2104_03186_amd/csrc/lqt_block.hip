@@ -23,9 +23,10 @@
 // K = R^{-T} V with V = R^{-1} L^T S F, and S' = F^T S F - V^T V + J.
 //
 // Phases (as in the wavefront classes): b_prep (constants, terminal value),
-// b_fold (chunk elements), b_chain (value at chunk starts, per instance),
-// b_final (values, gains, chunk maps), b_fchain (state at chunk starts),
-// b_roll (trajectory).
+// b_fold (chunk elements), b_chain (value at chunk starts, per instance; for
+// instances with many chunks b_tlevel + b_tanchor, the scan over the chunk
+// elements as a tree), b_final (values, gains, chunk maps), b_fchain (state
+// at chunk starts), b_roll (trajectory).
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"
@@ -39,32 +40,32 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 namespace blk64 {
 constexpr int N = 64, M = 32, NW = 4;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[8] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll",
-                                    "t64_fmat", "t64_fvec"};
+constexpr const char* kNames[10] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll",
+                                    "t64_fmat", "t64_fvec", "t64_tree", "t64_tanchor"};
 #include "lqt_block.inc"
 }  // namespace blk64
 
 namespace blk32 {
 constexpr int N = 32, M = 32, NW = 2;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[8] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll",
-                                    "b32_fmat", "b32_fvec"};
+constexpr const char* kNames[10] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll",
+                                    "b32_fmat", "b32_fvec", "b32_tree", "b32_tanchor"};
 #include "lqt_block.inc"
 }  // namespace blk32
 
 namespace blk32h {
 constexpr int N = 32, M = 16, NW = 2;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[8] = {"b32h_prep", "b32h_fold", "b32h_chain", "b32h_final", "b32h_fchain", "b32h_roll",
-                                   "b32h_fmat", "b32h_fvec"};
+constexpr const char* kNames[10] = {"b32h_prep", "b32h_fold", "b32h_chain", "b32h_final", "b32h_fchain", "b32h_roll",
+                                   "b32h_fmat", "b32h_fvec", "b32h_tree", "b32h_tanchor"};
 #include "lqt_block.inc"
 }  // namespace blk32h
 
 namespace blk16 {
 constexpr int N = 16, M = 16, NW = 1;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[8] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll",
-                                    "b16_fmat", "b16_fvec"};
+constexpr const char* kNames[10] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll",
+                                    "b16_fmat", "b16_fvec", "b16_tree", "b16_tanchor"};
 #include "lqt_block.inc"
 }  // namespace blk16
 

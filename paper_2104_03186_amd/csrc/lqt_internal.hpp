@@ -75,7 +75,7 @@ size_t wave_lds_bytes(int nmax);
 // with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
 int tile_class(int need);
 size_t tile_lds_bytes(int N);
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h);
 // Workgroup engines (N = 16, 32, 64; time-invariant except c; class 64:
 // n, p, pT <= 64 and m <= 32).

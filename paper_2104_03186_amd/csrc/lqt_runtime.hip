@@ -76,17 +76,20 @@ int eng_of(const lqt_routing& R, const lqt_problem& p) {
 }
 
 // Chunk length of a chunked-path instance.  Default: about 64 chunks per
-// instance, between 16 and 256 steps.  A plan tuned by lqt_tune uses about
-// `div` chunks per instance for the launch group, at least 16 steps each
-// (div = 1: one chunk, no element fold at all -- the instance is then solved
-// by the sequential down-sweep alone, which pays when a batch has enough
-// instances to fill the GPU).  The routing override wave_chunk fixes the
-// length.
+// instance, between 16 and 256 steps; an instance longer than kTreeT takes
+// 64-step chunks instead (at least 257 of them, scanned as a tree, so that
+// the per-chunk fold and down-sweep stay short).  A plan tuned by lqt_tune uses about `div` chunks per instance for
+// the launch group, at least 16 steps each (div = 1: one chunk, no element
+// fold at all -- the instance is then solved by the sequential down-sweep
+// alone, which pays when a batch has enough instances to fill the GPU).  The
+// routing override wave_chunk fixes the length.
 constexpr int kTuneDivs[] = {1, 4, 16, 64, 256};
+constexpr int64_t kTreeT = 16384;
 
 int wave_chunk(const lqt_routing& R, int64_t T, int div = 0) {
     if (R.wave_chunk >= 1 && R.wave_chunk <= 4096) return R.wave_chunk;
     if (div <= 0) {
+        if (T > kTreeT) return 64;
         const int64_t b = (T + 63) / 64;
         return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
     }
@@ -778,7 +781,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         const int eng = eng_of(plan->route, p0);
         const lqt::StageHook* hk = plan->prof.on ? &hook : nullptr;
         hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, gf32, s, hk)
-                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, fwd, gf32, s, hk);
+                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, gf32, s, hk);
         if (e == hipSuccess && m2)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, s,
                                 hk);
@@ -910,7 +913,7 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
         const int eng = eng_of(plan->route, p);
         if (e == hipSuccess)
             e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr)
-                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, fwd, f32, s, nullptr);
+                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr);
         if (e == hipSuccess && gi.traj)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p), d_inst, 1, gi.NC, s, nullptr);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));

@@ -16,10 +16,12 @@
 //   t_fold    per chunk: fold the one-step elements a_k (Section IV-B) with
 //             the combination rule (Section IV-A) into the chunk element;
 //   t_chain   per instance: value function at every chunk start, walking the
-//             chunks from the terminal value with the anchored combination;
+//             chunks from the terminal value with the anchored combination
+//             (instances with many chunks: t_tlevel + t_tanchor, the scan
+//             over the chunk elements as a tree);
 //   t_final   per chunk: down-sweep in Riccati form fused with the gain
 //             extraction (writes S, v, K, d) and the chunk's closed-loop map;
-//   g_fchain  per instance: state at every chunk start from x_0 (Method 1
+//   t_fchain  per instance: state at every chunk start from x_0 (Method 1
 //             affine maps, Section IV-C);
 //   t_roll    per chunk: u_k = -K_k x_k + d_k, x_{k+1} = F x_k + c + L u_k.
 #include <hip/hip_runtime.h>
@@ -219,35 +221,6 @@ __global__ __launch_bounds__(kW) void g_prep(const GInst* inst, int ninst, int N
 }
 
 // ---- forward pass ------------------------------------------------------------------
-
-__global__ __launch_bounds__(kW) void g_fchain(const GInst* inst, int ninst, int N) {
-    extern __shared__ __align__(16) double dyn[];
-    const int ii = blockIdx.x;
-    if (ii >= ninst) return;
-    const GInst& I = inst[ii];
-    const int lane = threadIdx.x;
-    const int n = I.n;
-    const WaveLds wl = wave_lds(N);
-    Slots s = slots_of(dyn, wl);
-    const InstWs ws = inst_ws(I);
-    const int64_t nn = (int64_t)n * n;
-    double* x = s.v[0];
-    double* t = s.v[1];
-    for (int j = lane; j < n; j += kW) x[j] = I.x0[j];
-    wsync();
-    for (int64_t c = 0; c < I.NC; ++c) {
-        for (int j = lane; j < n; j += kW) ws.xs[c * n + j] = x[j];
-        const double* mp = ws.map + c * val_doubles(n);
-        for (int r = lane; r < n; r += kW) {
-            double a = mp[nn + r];
-            for (int q = 0; q < n; ++q) a = fma(mp[r * n + q], x[q], a);
-            t[r] = a;
-        }
-        wsync();
-        for (int j = lane; j < n; j += kW) x[j] = t[j];
-        wsync();
-    }
-}
 
 // ============================================================================
 // Size-class kernels: every matrix is zero-padded to a compile-time N x N
@@ -766,6 +739,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const GInst& I = inst[ii];
+    if (ws_tree(I.eng, I.NC)) return;  // t_tlevel + t_tanchor
     const int lane = threadIdx.x;
     const int n = I.n;
     TSlots<N> s = tslots<N>(dyn);
@@ -807,6 +781,197 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
         vo = ws.val + c * val_doubles(n);
         tstore<N>(n, n, Sm, vo, n, lane);
         if (lane < n) vo[nn + lane] = v[lane];
+    }
+}
+
+// Chunk scan as a tree for instances with at least kTreeMinNC chunks (as on
+// the workgroup engines): level l replaces element c by E_c (x) E_{c+2^l}
+// with the general combination rule of Section IV-A; t_tanchor anchors the
+// suffixes on the terminal value (Section IV-B).  Records are n-dimensional.
+template <int N>
+__global__ __launch_bounds__(kW) void t_tlevel(const GInst* inst, int ninst, int64_t nchunks, int level) {
+    extern __shared__ __align__(16) double dyn[];
+    constexpr int ld = TL<N>::ld;
+    const int64_t gc = blockIdx.x;
+    if (gc >= nchunks) return;
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
+    const int64_t c = gc - I.chunk0;
+    if (!ws_tree(I.eng, I.NC) || c == 0) return;  // the first chunk's element is never needed
+    const int lane = threadIdx.x;
+    const int n = I.n;
+    const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
+    const InstWs ws = inst_ws(I);
+    const int64_t dist = int64_t(1) << level;
+    const double* src = level == 0 ? ws.agg : ws.tree + ((level - 1) & 1) * I.NC * ED;
+    double* dst = ws.tree + (level & 1) * I.NC * ED + c * ED;
+    const double* ex = src + c * ED;
+    if (c + dist >= I.NC) {  // nothing later at this distance: carried over
+        for (int64_t idx = lane; idx < ED; idx += kW) dst[idx] = ex[idx];
+        return;
+    }
+    const double* ey = src + (c + dist) * ED;
+    TSlots<N> s = tslots<N>(dyn);
+    double *XA = s.m[0], *XC = s.m[1], *XJ = s.m[2], *YA = s.m[3], *YC = s.m[4], *YJ = s.m[5];
+    double *Mm = s.m[6], *Mi = s.m[7], *T1 = s.m[8], *U1 = s.m[9], *W1 = s.m[10], *R1 = s.m[11];
+    double *xb = s.v[0], *xe = s.v[1], *yb = s.v[2], *ye = s.v[3], *y0 = s.v[4], *z = s.v[5], *w = s.v[6];
+    double *o1 = s.v[7], *o2 = s.v[8];
+    tload<N>(n, n, ex, n, XA, lane);
+    tload<N>(n, n, ex + nn + n, n, XC, lane);
+    tload<N>(n, n, ex + 2 * nn + 2 * n, n, XJ, lane);
+    tload<N>(n, n, ey, n, YA, lane);
+    tload<N>(n, n, ey + nn + n, n, YC, lane);
+    tload<N>(n, n, ey + 2 * nn + 2 * n, n, YJ, lane);
+    tvec_load<N>(n, ex + nn, xb, lane);
+    tvec_load<N>(n, ex + 2 * nn + n, xe, lane);
+    tvec_load<N>(n, ey + nn, yb, lane);
+    tvec_load<N>(n, ey + 2 * nn + n, ye, lane);
+    // M = I + C_x J_y (the identity on the padding)
+    tgemm<N, false, false>(XC, YJ, Mm, 1.0, 0.0, lane);
+    if (lane < N) Mm[lane * ld + lane] += 1.0;
+    wsync();
+    tinv<N>(Mm, Mi, lane);
+    // y0 = b_x + C_x eta_y ; z = M^{-1} y0 ; w = eta_y - J_y b_x
+    tgemv<N, false>(XC, ye, y0, 1.0, 0.0, lane);
+    if (lane < N) y0[lane] += xb[lane];
+    wsync();
+    tgemv<N, false>(Mi, y0, z, 1.0, 0.0, lane);
+    tgemv<N, false>(YJ, xb, w, -1.0, 0.0, lane);
+    if (lane < N) w[lane] += ye[lane];
+    wsync();
+    tgemm<N, false, false>(Mi, XA, T1, 1.0, 0.0, lane);        // T = M^{-1} A_x
+    tgemm<N, false, false>(Mi, XC, U1, 1.0, 0.0, lane);        // M^{-1} C_x (symmetric)
+    tgemm<N, false, false>(YA, U1, W1, 1.0, 0.0, lane);        // A_y M^{-1} C_x
+    tgemm<N, false, true, true>(W1, YA, R1, 1.0, 0.0, lane);   // A_y M^{-1} C_x A_y^T
+    for (int idx = lane; idx < N * N; idx += kW) R1[(idx / N) * ld + idx % N] += YC[(idx / N) * ld + idx % N];
+    wsync();
+    tstore<N>(n, n, R1, dst + nn + n, n, lane);                // C
+    tgemm<N, false, false>(YA, T1, W1, 1.0, 0.0, lane);        // A = A_y T
+    tstore<N>(n, n, W1, dst, n, lane);
+    tgemm<N, false, false>(YJ, XA, U1, 1.0, 0.0, lane);        // J_y A_x
+    tgemm<N, true, false, true>(T1, U1, R1, 1.0, 0.0, lane);   // T^T J_y A_x
+    for (int idx = lane; idx < N * N; idx += kW) R1[(idx / N) * ld + idx % N] += XJ[(idx / N) * ld + idx % N];
+    wsync();
+    tstore<N>(n, n, R1, dst + 2 * nn + 2 * n, n, lane);        // J
+    tgemv<N, false>(YA, z, o1, 1.0, 0.0, lane);                // A_y z
+    tgemv<N, true>(T1, w, o2, 1.0, 0.0, lane);                 // T^T w
+    if (lane < n) {
+        dst[nn + lane] = o1[lane] + yb[lane];                   // b
+        dst[2 * nn + n + lane] = o2[lane] + xe[lane];           // eta
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kW) void t_tanchor(const GInst* inst, int ninst, int64_t nchunks, int levels) {
+    extern __shared__ __align__(16) double dyn[];
+    constexpr int ld = TL<N>::ld;
+    const int64_t gc = blockIdx.x;
+    if (gc >= nchunks) return;
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
+    const int64_t c = gc - I.chunk0;
+    if (!ws_tree(I.eng, I.NC)) return;
+    const int lane = threadIdx.x;
+    const int n = I.n;
+    const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
+    const InstWs ws = inst_ws(I);
+    const CstW cl = cst_layout(n, I.m, I.p);
+    if (c == 0) {  // the terminal value (the value at chunk 0's start is never read)
+        double* vo = ws.val + I.NC * val_doubles(n);
+        for (int64_t idx = lane; idx < nn; idx += kW) vo[idx] = ws.cst[cl.ST + idx];
+        if (lane < n) vo[nn + lane] = ws.cst[cl.VT + lane];
+        return;
+    }
+    const double* e = (levels > 0 ? ws.tree + ((levels - 1) & 1) * I.NC * ED : ws.agg) + c * ED;
+    TSlots<N> s = tslots<N>(dyn);
+    double *EA = s.m[0], *EC = s.m[1], *EJ = s.m[2], *Sm = s.m[3];
+    double *Mm = s.m[4], *Mi = s.m[5], *T1 = s.m[6], *P = s.m[7];
+    double *Eb = s.v[0], *Ee = s.v[1], *v = s.v[2], *t = s.v[3], *nv = s.v[4];
+    tload<N>(n, n, ws.cst + cl.ST, n, Sm, lane);
+    tvec_load<N>(n, ws.cst + cl.VT, v, lane);
+    tload<N>(n, n, e, n, EA, lane);
+    tload<N>(n, n, e + nn + n, n, EC, lane);
+    tload<N>(n, n, e + 2 * nn + 2 * n, n, EJ, lane);
+    tvec_load<N>(n, e + nn, Eb, lane);
+    tvec_load<N>(n, e + 2 * nn + n, Ee, lane);
+    // (S, v) <- E (x) (0, 0, 0, v_T, S_T)
+    tgemm<N, false, false>(EC, Sm, Mm, 1.0, 0.0, lane);
+    if (lane < N) Mm[lane * ld + lane] += 1.0;
+    wsync();
+    tinv<N>(Mm, Mi, lane);
+    tgemm<N, false, false>(Mi, EA, T1, 1.0, 0.0, lane);
+    tgemv<N, false>(Sm, Eb, t, -1.0, 0.0, lane);
+    if (lane < N) t[lane] += v[lane];
+    wsync();
+    tgemv<N, true>(T1, t, nv, 1.0, 0.0, lane);
+    tgemm<N, false, false>(Sm, EA, P, 1.0, 0.0, lane);
+    tgemm<N, true, false, true>(T1, P, Sm, 1.0, 0.0, lane);
+    for (int idx = lane; idx < N * N; idx += kW) Sm[(idx / N) * ld + idx % N] += EJ[(idx / N) * ld + idx % N];
+    if (lane < N) v[lane] = nv[lane] + Ee[lane];
+    wsync();
+    double* vo = ws.val + c * val_doubles(n);
+    tstore<N>(n, n, Sm, vo, n, lane);
+    if (lane < n) vo[nn + lane] = v[lane];
+}
+
+// State at every chunk start from x_0 (x_{c+1} = Phi_c x_c + phi_c), one
+// wavefront per instance: lane l holds row l % N of the maps' column group
+// l / N (N^2 / 64 columns) and the maps of the next kTPre chunks are loaded
+// into registers ahead of their use.
+constexpr int kTPre = 4;
+
+template <int N>
+__global__ __launch_bounds__(kW) void t_fchain(const GInst* inst, int ninst) {
+    extern __shared__ __align__(16) double dyn[];
+    constexpr int G = kW / N;    // column groups
+    constexpr int QW = N / G;    // columns per lane
+    const int ii = blockIdx.x;
+    if (ii >= ninst) return;
+    const GInst& I = inst[ii];
+    const int lane = threadIdx.x;
+    const int n = I.n;
+    const int r = lane % N, g = lane / N;
+    const bool act = r < n;
+    const InstWs ws = inst_ws(I);
+    const int64_t VD = val_doubles(n);
+    double* x = dyn;             // N (zero beyond n)
+    double* part = x + N;        // G x N partial products
+    if (lane < N) x[lane] = (lane < n) ? I.x0[lane] : 0.0;
+    double buf[kTPre][QW + 1];
+    auto load = [&](int64_t c, double* d) {
+        if (c < I.NC) {
+            const double* mp = ws.map + c * VD;
+#pragma unroll
+            for (int q = 0; q < QW; ++q) {
+                const int col = g * QW + q;
+                d[q] = (act && col < n) ? mp[(int64_t)r * n + col] : 0.0;
+            }
+            d[QW] = (act && g == 0) ? mp[(int64_t)n * n + r] : 0.0;
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < kTPre; ++j) load(j, buf[j]);
+    wsync();
+#pragma unroll 1
+    for (int64_t c0 = 0; c0 < I.NC; c0 += kTPre) {
+#pragma unroll
+        for (int j = 0; j < kTPre; ++j) {
+            const int64_t c = c0 + j;
+            if (c < I.NC) {
+                if (lane < n) ws.xs[c * n + lane] = x[lane];
+                double a = buf[j][QW];
+#pragma unroll
+                for (int q = 0; q < QW; ++q) a = fma(buf[j][q], x[g * QW + q], a);
+                part[g * N + r] = a;
+                load(c + kTPre, buf[j]);
+                wsync();
+                if (lane < N) {
+                    double y = part[lane];
+#pragma unroll
+                    for (int v = 1; v < G; ++v) y += part[v * N + lane];
+                    x[lane] = y;
+                }
+                wsync();
+            }
+        }
     }
 }
 
@@ -1024,19 +1189,22 @@ template <int N>
 struct TileNames;
 template <>
 struct TileNames<8> {
-    static constexpr const char* n[6] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll"};
+    static constexpr const char* n[8] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll",
+                                          "t8_tree", "t8_tanchor"};
 };
 template <>
 struct TileNames<16> {
-    static constexpr const char* n[6] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll"};
+    static constexpr const char* n[8] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll",
+                                          "t16_tree", "t16_tanchor"};
 };
 template <>
 struct TileNames<32> {
-    static constexpr const char* n[6] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll"};
+    static constexpr const char* n[8] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll",
+                                          "t32_tree", "t32_tanchor"};
 };
 
 template <int N, typename OT>
-static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
+static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, hipStream_t s,
                      const StageHook* h) {
     const char* const* nm = TileNames<N>::n;
     const size_t lds = tile_lds_bytes(N);
@@ -1044,7 +1212,8 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
     static bool attr = false;
     if (!attr) {
         const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N, OT>,
-                            (const void*)t_roll<N, OT>, (const void*)g_prep, (const void*)g_fchain};
+                            (const void*)t_roll<N, OT>, (const void*)g_prep, (const void*)t_tlevel<N>,
+                            (const void*)t_tanchor<N>};
         for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
@@ -1055,6 +1224,17 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
     {
         WStage st(h, nm[1], s);
         t_fold<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+    }
+    if (max_nc >= kTreeMinNC) {
+        int levels = 0;
+        while ((int64_t(1) << levels) < max_nc - 1) ++levels;
+        {
+            WStage st(h, nm[6], s);
+            for (int l = 0; l < levels; ++l)
+                t_tlevel<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, l);
+        }
+        WStage st(h, nm[7], s);
+        t_tanchor<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, levels);
     }
     {
         WStage st(h, nm[2], s);
@@ -1067,7 +1247,7 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
     if (want_fwd) {
         {
             WStage st(h, nm[4], s);
-            g_fchain<<<ninst, kW, glds, s>>>(d_inst, ninst, N);
+            t_fchain<N><<<ninst, kW, sizeof(double) * (1 + kW / N) * N, s>>>(d_inst, ninst);
         }
         WStage st(h, nm[5], s);
         t_roll<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
@@ -1075,21 +1255,21 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, bool want_
 }
 
 template <typename OT>
-static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, hipStream_t s,
-                             const StageHook* h) {
+static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
+                             hipStream_t s, const StageHook* h) {
     switch (N) {
-        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
-        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
-        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, want_fwd, s, h); break;
+        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
+        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
+        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, bool want_fwd, bool f32,
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h) {
-    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, want_fwd, s, h)
-               : tile_typed<double>(N, d_inst, ninst, nchunks, want_fwd, s, h);
+    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, max_nc, want_fwd, s, h)
+               : tile_typed<double>(N, d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
 }
 
 }  // namespace lqt
