@@ -38,12 +38,12 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector and FP32 matrix (dense)
 # plain-copy calibration (`bench.py --workload copy`: FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Reported only while the kernel sources hash to the
 # version the counters were taken on.
-TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_lane.hpp", "lqt_ops.hpp", "lqt_regmath.hpp", "lqt_internal.hpp")
+TRAFFIC_SOURCES = ("lqt_small.hip", "lqt_lane.hpp", "lqt_ops.hpp", "lqt_regmath.hpp")
 TRAFFIC = {
     ("bwd_final", "fp64", 1_000_000): {
         "bytes_per_launch": 310_378_720,
         "fetch_kib": 26487.2, "write_kib": 250129.8, "fetch_scale": 2.0, "write_scale": 1.0,
-        "src_sha256": "f3062b7ba5dd28357077d134e106c390e8e753bc92a4c0920ab11597f5481a0b",
+        "src_sha256": "41c9c1b31124fb8f344f38941f461f844bf0ab5fad57ae237c6977be31bbdd0f",
     },
 }
 
@@ -207,6 +207,13 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
     plan.profile(False)
     plan.profile_select(None)
     per_solve = timing_stats(timed_solves(torch, stream, lambda: plan.solve([dp], [do], stream), 10))
+    alt = None
+    if T <= 16384:  # the default route here is the batched lane kernel; the lane pipeline beside it
+        plan.set_routing(path="small")
+        for _ in range(3):
+            plan.solve([dp], [do], stream)
+        alt = timing_stats(timed_solves(torch, stream, lambda: plan.solve([dp], [do], stream), 10))
+        plan.set_routing()
     plan.close()
 
     ms_per_step = ms_total / steps
@@ -232,7 +239,8 @@ def run_single(args, api, inputs, torch, prec, steps, warmup, with_cpu, trajecto
         sps, secs, reps = oracle.time_solve([prob], min_seconds=args.cpu_seconds)
         cpu = {"value": round(sps, 1), "unit": "steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"{reps} full sequential FP64 solve(s) of the same T={T} instance ({secs:.1f} s)"}
-    return {"value": value, "ms_per_step": ms_per_step, "ms_per_solve_stats": per_solve, "status": status,
+    return {"value": value, "ms_per_step": ms_per_step, "ms_per_solve_stats": per_solve,
+            "lane_pipeline_ms_per_solve_stats": alt, "status": status,
             "rel_err": rel_err,
             "stages_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in stages_all.items()},
             "roofline": roofline, "path_roofline": path, "cpu_baseline": cpu, "wall_s": wall}
@@ -813,6 +821,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 4),
         "ms_per_solve_stats": main_res["ms_per_solve_stats"],
+        "lane_pipeline_ms_per_solve_stats": main_res["lane_pipeline_ms_per_solve_stats"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -849,6 +858,8 @@ def main():
         note("finite state done")
         out["block_sweep"] = run_blocks(args, api, inputs, torch)
         note("block sweep done")
+        out["partial_condensing"] = run_condensing(args, api, inputs, torch)
+        note("partial condensing done")
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed", with_cpu)
         note("batched done")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed", with_cpu)
