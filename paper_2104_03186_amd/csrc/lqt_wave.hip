@@ -239,6 +239,7 @@ struct TL {
 };
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
+constexpr bool kT8Mfma = true;  // class-8 products on the matrix cores
 
 // C = alpha op(A) op(B) + beta C on the matrix cores (N = 16, 32): 16 x 16
 // output tiles, 16 x 16 x 4 FP64 MFMA per k-slice.  Operand layout (measured
@@ -281,6 +282,42 @@ WDI void tgemm_mfma(const double* A, const double* B, double* C, double alpha, d
     wsync();
 }
 
+// The same for N = 8 on the matrix cores: one 16 x 16 output tile whose rows
+// and columns beyond 8 are never read (their lanes supply zeros) and a
+// reduction of two 4-deep steps; per lane four LDS reads and two writes
+// instead of the sixteen reads of the per-lane VALU tile.
+template <bool TA, bool TB, bool SYM>
+WDI void tgemm8_mfma(const double* A, const double* B, double* C, double alpha, double beta, int lane) {
+    constexpr int ld = TL<8>::ld;
+    const int i0 = lane & 15, kk = lane >> 4;
+    const bool in = i0 < 8;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+        const int kx = 4 * s4 + kk;
+        const double a = in ? (TA ? A[kx * ld + i0] : A[i0 * ld + kx]) : 0.0;
+        const double b = in ? (TB ? B[i0 * ld + kx] : B[kx * ld + i0]) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    double out[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {  // rows kk + 4 v < 8 of column i0
+        const int r = kk + 4 * v;
+        out[v] = (beta == 0.0 || !in) ? alpha * acc[v] : fma(alpha, acc[v], beta * C[r * ld + i0]);
+    }
+    if (SYM) wsync();
+    if (in) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = kk + 4 * v;
+            if (SYM && r > i0) continue;  // written as the mirror of (i0, r)
+            C[r * ld + i0] = out[v];
+            if (SYM) C[i0 * ld + r] = out[v];
+        }
+    }
+    wsync();
+}
+
 // C = alpha op(A) op(B) + beta C, all N x N.  sym: the result is symmetric;
 // only tiles on or above the diagonal are computed and each value is written
 // to both mirrored positions (exactly symmetric).
@@ -288,6 +325,10 @@ template <int N, bool TA, bool TB, bool SYM = false>
 WDI void tgemm(const double* A, const double* B, double* C, double alpha, double beta, int lane) {
     if constexpr (N >= 16) {
         tgemm_mfma<N, TA, TB, SYM>(A, B, C, alpha, beta, lane);
+        return;
+    }
+    if constexpr (N == 8 && kT8Mfma) {
+        tgemm8_mfma<TA, TB, SYM>(A, B, C, alpha, beta, lane);
         return;
     }
     constexpr int ld = TL<N>::ld, T = TL<N>::T;

@@ -2,7 +2,8 @@
 with eager work and synchronisations between the replays and the input data
 changed in place between them, equals the same call made directly on the
 same data, bit for bit, every time -- for a batch that spans every path
-(batched lane kernel, lane pipeline, wavefront and workgroup engines), for
+(batched lane kernel, lane pipeline, wavefront and workgroup engines, the
+chunk elements of a long instance scanned as a tree), for
 the iterated linearisation of the nonlinear extension (Section IV-D) on the
 lane pipeline and on the wavefront engine, and with the forward-prefix
 trajectory (its element scan on a second stream).
@@ -42,7 +43,8 @@ def batch_problems():
             inputs.random_problem(6, 3, 700, seed=31),                    # wavefront engine, class 8
             inputs.diag_problem(16, 8, 1500, 2, 7),                       # workgroup engine, class 16
             inputs.random_problem(12, 5, 400, seed=32, per_step=1 | 2),   # wavefront engine, per-step
-            inputs.random_problem(3, 2, 900, seed=33)]                    # batched lane kernel, offsets
+            inputs.random_problem(3, 2, 900, seed=33),                    # batched lane kernel, offsets
+            inputs.diag_problem(12, 6, 17000, 2, 8)]                      # workgroup engine, chunk tree
 
 
 @pytest.mark.parametrize("traj", ["maps", "prefix"])
@@ -73,7 +75,7 @@ def test_batch_replays_equal_direct(api, traj):
                 for f in FAMILIES:
                     assert np.array_equal(ga[f], gb[f]), (rep, i, f)
             if rep == REPLAYS:  # the last replay against the oracle on the data it saw
-                for i in (0, 2, 3):
+                for i in (0, 2, 3, 6):
                     ref = oracle.solve(probs[i])
                     got = g_out[i].host()
                     assert max(err(got[f], ref[f]) for f in FAMILIES) <= 1e-10, i

@@ -85,6 +85,8 @@ def test_served_equals_alone_and_oracle(api):
         T = int(np.exp(rng.uniform(np.log(64), np.log(1500 if n > 16 else 5000))))
         probs.append(served_request(n, T, i))
     probs.append(inputs.tracking_problem(n=4, m=2, T=9000, instance=7))  # lane-per-element path
+    probs.append(served_request(12, 20000, 40))  # long: chunk elements scanned as a tree
+    probs.append(served_request(6, 18000, 41))   # long, wavefront engine: tree
     _say("served mix of", len(probs), "requests")
     plan = api.Plan(32, 16, prec="mixed")
     dps = [api.DeviceProblem(p) for p in probs]
