@@ -780,7 +780,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const GInst& I = inst[ii];
-    if (ws_tree(I.eng, I.NC)) return;  // t_tlevel + t_tanchor
+    if (ws_tree(I.NC)) return;  // t_tlevel + t_tanchor
     const int lane = threadIdx.x;
     const int n = I.n;
     TSlots<N> s = tslots<N>(dyn);
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(kW) void t_tlevel(const GInst* inst, int ninst, int
     if (gc >= nchunks) return;
     const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
-    if (!ws_tree(I.eng, I.NC) || c == 0) return;  // the first chunk's element is never needed
+    if (!ws_tree(I.NC) || c == 0) return;  // the first chunk's element is never needed
     const int lane = threadIdx.x;
     const int n = I.n;
     const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
@@ -909,7 +909,7 @@ __global__ __launch_bounds__(kW) void t_tanchor(const GInst* inst, int ninst, in
     if (gc >= nchunks) return;
     const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
-    if (!ws_tree(I.eng, I.NC)) return;
+    if (!ws_tree(I.NC)) return;
     const int lane = threadIdx.x;
     const int n = I.n;
     const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);

@@ -99,7 +99,7 @@ __host__ __device__ inline int64_t ws_opr_doubles(int d, int64_t B, int p) { ret
 // doubling (log2 NC levels, every chunk in parallel) instead of one walk over
 // the chunks; two more element buffers for the levels.
 constexpr int64_t kTreeMinNC = 128;
-__host__ __device__ inline bool ws_tree(int /*eng*/, int64_t NC) { return NC >= kTreeMinNC; }
+__host__ __device__ inline bool ws_tree(int64_t NC) { return NC >= kTreeMinNC; }
 
 // cst | agg[NC] (chunk elements; in the operator form agg[0] holds the common
 //     matrix part) | val[NC + 1] (value at chunk starts and T) | map[NC] (chunk
@@ -109,7 +109,7 @@ __host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int6
                                               bool has_c = true) {
     const int d = ws_dim(n, eng);
     const int64_t ops = ws_op_form(eng, has_c) ? ws_ops_doubles(d, B) + ws_opr_doubles(d, B, p) : 0;
-    const int64_t tree = ws_tree(eng, NC) ? 2 * NC * elem_doubles(d) : 0;
+    const int64_t tree = ws_tree(NC) ? 2 * NC * elem_doubles(d) : 0;
     return ws_cst_doubles(n, m, p, eng) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
            NC * d + ops + tree + 32;
 }
