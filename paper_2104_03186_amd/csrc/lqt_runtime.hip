@@ -82,14 +82,16 @@ int eng_of(const lqt_routing& R, const lqt_problem& p) {
 // the launch group, at least 16 steps each (div = 1: one chunk, no element
 // fold at all -- the instance is then solved by the sequential down-sweep
 // alone, which pays when a batch has enough instances to fill the GPU).  The
-// routing override wave_chunk fixes the length.
+// routing override wave_chunk fixes the length.  Plans that recover the
+// trajectory by forward prefixes keep the longer chunks: their forward walk
+// over the chunk elements is sequential in the number of chunks.
 constexpr int kTuneDivs[] = {1, 4, 16, 64, 256};
 constexpr int64_t kTreeT = 16384;
 
-int wave_chunk(const lqt_routing& R, int64_t T, int div = 0) {
+int wave_chunk(const lqt_routing& R, int64_t T, int div = 0, bool prefix = false) {
     if (R.wave_chunk >= 1 && R.wave_chunk <= 4096) return R.wave_chunk;
     if (div <= 0) {
-        if (T > kTreeT) return 64;
+        if (T > kTreeT && !prefix) return 64;
         const int64_t b = (T + 63) / 64;
         return (int)std::max<int64_t>(16, std::min<int64_t>(256, b));
     }
@@ -310,7 +312,8 @@ Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool 
 }
 
 int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
-    return wave_chunk(plan->route, p.T, plan->tune_div[group_key(plan->route, p)]);
+    return wave_chunk(plan->route, p.T, plan->tune_div[group_key(plan->route, p)],
+                      plan->desc.trajectory == LQT_TRAJ_PREFIX);
 }
 
 // Workspace of one wavefront-path instance, and of its K, d scratch when the
@@ -1299,7 +1302,7 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
                 }
         // and for one wavefront-path instance of the largest dimensions
         {
-            const int64_t B = wave_chunk(p->route, desc->max_steps);
+            const int64_t B = wave_chunk(p->route, desc->max_steps, 0, desc->trajectory == LQT_TRAJ_PREFIX);
             const int64_t NC = (desc->max_steps + B - 1) / B;
             const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
             const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC),

@@ -135,3 +135,18 @@ def test_batch_of_tree_and_chain_instances_equals_alone(api):
         for f in FAMILIES:
             assert np.array_equal(mix[i][1][f], alone[1][f]), (i, f)
     check(mix[0][1], oracle.solve(probs[0]), TOL["fp64"])
+
+
+def test_status_codes_and_isolation(api):
+    """A tree instance whose U is not positive definite (LQT_ENOTPD) and one
+    with a non-finite reference (LQT_ENONFINITE) fail alone; the instance
+    beside them is unaffected."""
+    good = SHAPES["class16_offsets"](16 * 140)
+    bad = SHAPES["class16_offsets"](16 * 140)
+    bad.U = -np.eye(bad.m)
+    nan = SHAPES["wave8"](16 * 150)
+    nan.r[700, 0] = np.nan
+    _say("tree status codes")
+    res = solve(api, [good, bad, nan])
+    assert [st for st, _ in res] == [0, 3, 4]
+    check(res[0][1], oracle.solve(good), TOL["fp64"])

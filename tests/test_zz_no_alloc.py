@@ -4,7 +4,8 @@ Two calls in a row on one plan through the C ABI, the second with a smaller
 instance, each compared with lqt_solve of the same instance (the same
 kernels and chunking: equal bit for bit) and with the oracle (the FP64 gate
 of the parity tests); a generalised-cost instance, a wavefront-engine
-instance and a MIXED plan; the size limit of the static workspace.
+instance, a long instance whose chunk elements are scanned as a tree and a
+MIXED plan; the size limit of the static workspace.
 """
 import sys
 
@@ -85,6 +86,7 @@ def test_generalised_and_workgroup_engine(api):
     try:
         for prob in (inputs.generalised_problem(4, 2, 9000, seed=21, p=3),
                      inputs.diag_problem(16, 8, 2000, 2, 5),
+                     inputs.diag_problem(12, 6, 20000, 2, 6),  # 313 chunks: scanned as a tree
                      inputs.generalised_problem(12, 5, 700, seed=22, p=8, per_step=2)):
             _say("noalloc", prob.n, prob.m, prob.T)
             got, alone = both(api, plan, prob, torch.float64)
