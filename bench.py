@@ -607,6 +607,44 @@ def run_condensing(args, api, inputs, torch):
     return {"workload": f"partial condensing, tracking n=4 m=2 T={T} fp64, block length B", "by_block": res}
 
 
+def run_state_scaling(args, api, inputs, torch, with_cpu=True):
+    """State dimension (Section VI-C): the chain of N masses (n = 2N, m = 2)
+    over a 10 s horizon in T steps, one instance per solve, FP64; device time
+    per solve (median of args.block_steps solves) beside the oracle's
+    sequential solve of the same instance on one host core."""
+    res = {}
+    for N in (2, 4, 8, 16, 32):
+        for T in (100, 1000):
+            prob = inputs.mass_spring_problem(N, T)
+            plan = api.Plan(2 * N, 2, prec="fp64", device=0)
+            try:
+                dp = api.DeviceProblem(prob)
+                do = api.DeviceOutputs(prob.n, prob.m, T)
+                stream = torch.cuda.current_stream(0)
+                for _ in range(3):
+                    plan.solve([dp], [do], stream)
+                torch.cuda.synchronize()
+                st = int(do.status.item())
+                g = timing_stats(timed_solves(torch, stream, lambda: plan.solve([dp], [do], stream),
+                                              args.block_steps))
+            finally:
+                plan.close()
+            row = {"n": 2 * N, "status": st, "gpu_ms_per_solve": g}
+            if with_cpu:
+                import oracle
+
+                ts = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    oracle.solve(prob)
+                    ts.append((time.perf_counter() - t0) * 1e3)
+                row["oracle_ms_per_solve"] = round(float(np.median(ts)), 3)
+                row["oracle_over_gpu"] = round(row["oracle_ms_per_solve"] / g["median"], 1)
+            res[f"N{N}_T{T}"] = row
+    return {"workload": "mass-spring-damper chain, n = 2N, m = 2, 10 s horizon, FP64, one instance", "by_size": res,
+            "oracle_host": host_cpu() if with_cpu else None}
+
+
 def run_copy(args, torch):
     """Plain device copy of 256 MiB (float64), three times: the calibration of
     the HBM byte counters (a copy moves exactly its size in each direction)."""
@@ -748,7 +786,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--workload", choices=("all", "single", "batched", "dense", "serving", "nonlinear", "finite",
-                                           "blocks", "condensing", "copy"), default="all")
+                                           "blocks", "condensing", "scaling", "copy"), default="all")
     ap.add_argument("--prec", choices=("fp64", "mixed"), default=None,
                     help="precision of a --workload single/batched/serving run")
     ap.add_argument("--trajectory", choices=("maps", "prefix"), default="maps",
@@ -801,6 +839,9 @@ def main():
         return
     if args.workload == "condensing":
         print(json.dumps(run_condensing(args, api, inputs, torch)), flush=True)
+        return
+    if args.workload == "scaling":
+        print(json.dumps(run_state_scaling(args, api, inputs, torch, not args.no_cpu_baseline)), flush=True)
         return
     if args.workload == "finite":
         print(json.dumps(run_finite(args, api, inputs, torch, not args.no_cpu_baseline)), flush=True)
@@ -860,6 +901,8 @@ def main():
         note("block sweep done")
         out["partial_condensing"] = run_condensing(args, api, inputs, torch)
         note("partial condensing done")
+        out["state_scaling"] = run_state_scaling(args, api, inputs, torch, not args.no_cpu_baseline)
+        note("state scaling done")
         out["batched_mixed"] = run_batched(args, api, inputs, torch, "mixed", with_cpu)
         note("batched done")
         out["dense_mixed"] = run_dense(args, api, inputs, torch, "mixed", with_cpu)

@@ -273,6 +273,49 @@ class UnicycleProblem:
     p: int = 3
 
 
+def mass_spring_problem(N: int, T: int, horizon: float = 10.0, mass: float = 1.0, spring: float = 1.0,
+                        damper: float = 0.2, x_weight: float = 1.0, u_weight: float = 1.0) -> LQTProblem:
+    """Chain of N masses joined by springs and dampers, forces on the first
+    and the last mass (the state-dimension experiment, Section VI-C): state
+    (y_1, y_1', ..., y_N, y_N'), n = 2N, m = 2, driven to the origin from
+    y_1 = y_{floor(N/2)+1} = 1 over `horizon` seconds in T steps.  Zero-order
+    hold discretisation in closed form: the exponential of the augmented
+    matrix [[A_c, B_c], [0, 0]] dt gives F and L.  The cost weights are not
+    given for this experiment; X = x_weight I (all states, reference 0),
+    U = u_weight I, X_T = X."""
+    import scipy.linalg
+
+    n, m = 2 * N, 2
+    Ac = np.zeros((n, n))
+    Bc = np.zeros((n, m))
+    k, d = spring / mass, damper / mass
+    for i in range(N):
+        yi, vi = 2 * i, 2 * i + 1
+        Ac[yi, vi] = 1.0
+        Ac[vi, yi] = -2.0 * k
+        Ac[vi, vi] = -2.0 * d
+        for j in (i - 1, i + 1):  # neighbours (the chain's ends have one)
+            if 0 <= j < N:
+                Ac[vi, 2 * j] = k
+                Ac[vi, 2 * j + 1] = d
+    Bc[1, 0] = 1.0 / mass
+    Bc[2 * (N - 1) + 1, 1] = -1.0 / mass
+    dt = horizon / T
+    aug = np.zeros((n + m, n + m))
+    aug[:n, :n] = Ac
+    aug[:n, n:] = Bc
+    E = scipy.linalg.expm(aug * dt)
+    F = np.ascontiguousarray(E[:n, :n])
+    L = np.ascontiguousarray(E[:n, n:])
+    x0 = np.zeros(n)
+    x0[0] = 1.0
+    x0[2 * (N // 2)] = 1.0
+    eye = np.eye(n)
+    return LQTProblem(n=n, m=m, p=n, pT=n, T=T, per_step=0, F=F, c=None, L=L, H=eye.copy(),
+                      X=x_weight * eye, U=u_weight * np.eye(m), r=np.zeros((T, n)), HT=eye.copy(),
+                      XT=x_weight * eye, rT=np.zeros(n), x0=x0)
+
+
 def race_track(T: int, dt: float = 0.1, omega: float = 0.12):
     """A closed synthetic track (the paper's track is shown only in a figure):
     P(phi) = (50 cos phi, 30 sin phi + 8 sin 2 phi), phi = omega t, driven
