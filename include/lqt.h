@@ -247,14 +247,27 @@ int32_t lqt_graphs_recorded(lqt_plan_t plan);
  *               wavefront engine even when they are time-invariant;
  *   lane_chunk: steps per lane of the lane pipeline, 1..1024;
  *   wave_chunk: steps per chunk of the chunked engines, 1..4096 (takes
- *               precedence over a tuned chunk length).
- * The chunking changes only the association order of the scan.  NULL restores
- * the automatic choices.  LQT_EINVAL for values outside these ranges. */
+ *               precedence over a tuned chunk length);
+ *   tree:       how the chunked engines scan an instance's chunks (the value
+ *               at every chunk start from the chunk elements, the state at
+ *               every chunk start from the chunk maps): 1 = as trees,
+ *               recursive doubling in about log2(chunks) dependent steps
+ *               (Section II-C), for every instance of two chunks or more,
+ *               with chunks of 8 to 64 steps (about as many chunks as the
+ *               GPU runs side by side) unless wave_chunk or lqt_tune fixes
+ *               the length; 2 = as walks over the chunks in sequence; 0 =
+ *               trees from 128 chunks on.  Trees do about log2(chunks) times
+ *               the work of the walks: they pay when a launch has too few
+ *               instances to fill the GPU (a lone instance, for latency).
+ * The chunking and the tree choice change only the association order of the
+ * scan.  NULL restores the automatic choices.  LQT_EINVAL for values outside
+ * these ranges. */
 typedef struct {
     int32_t path;
     int32_t block;
     int32_t lane_chunk;
     int32_t wave_chunk;
+    int32_t tree;
 } lqt_routing;
 
 lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing *routing);

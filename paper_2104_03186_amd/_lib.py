@@ -71,7 +71,7 @@ class PlanDesc(ctypes.Structure):
 
 class Routing(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32), ("lane_chunk", ctypes.c_int32),
-                ("wave_chunk", ctypes.c_int32)]
+                ("wave_chunk", ctypes.c_int32), ("tree", ctypes.c_int32)]
 
 
 class ServeStats(ctypes.Structure):

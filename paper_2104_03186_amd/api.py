@@ -214,15 +214,17 @@ class Plan:
         return n
 
     def set_routing(self, path: Optional[str] = None, wave_engine_only: bool = False, lane_chunk: int = 0,
-                    wave_chunk: int = 0) -> None:
+                    wave_chunk: int = 0, tree: Optional[bool] = None) -> None:
         """Routing and chunking overrides of this plan (lqt_set_routing):
         path "small" (lane pipeline wherever it applies), "wave" (chunked
         engines) or "batch" (batched lane kernel wherever it applies),
         wave_engine_only keeps the classes 16/32 off the workgroup
-        engines, lane_chunk / wave_chunk fix the chunk lengths (0: automatic).
-        Called with no arguments it restores the automatic choices."""
+        engines, lane_chunk / wave_chunk fix the chunk lengths (0: automatic),
+        tree True / False scans the chunks of every chunked instance as trees /
+        as walks (None: trees from 128 chunks on).  Called with no arguments it
+        restores the automatic choices."""
         r = _lib.Routing(path=_PATH[path], block=1 if wave_engine_only else 0, lane_chunk=int(lane_chunk or 0),
-                         wave_chunk=int(wave_chunk or 0))
+                         wave_chunk=int(wave_chunk or 0), tree=0 if tree is None else (1 if tree else 2))
         _lib.check(_lib.load().lqt_set_routing(self._h, ctypes.byref(r)), self._h)
 
     def _check_dtype(self, out: DeviceOutputs) -> None:

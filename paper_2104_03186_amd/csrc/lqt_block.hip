@@ -24,9 +24,10 @@
 //
 // Phases (as in the wavefront classes): b_prep (constants, terminal value),
 // b_fold (chunk elements), b_chain (value at chunk starts, per instance; for
-// instances with many chunks b_tlevel + b_tanchor, the scan over the chunk
+// instances with tree set b_tlevel + b_tanchor, the scan over the chunk
 // elements as a tree), b_final (values, gains, chunk maps), b_fchain (state
-// at chunk starts), b_roll (trajectory).
+// at chunk starts; b_ftlevel, a tree over the chunk maps, for instances with
+// tree set), b_roll (trajectory).
 #include <hip/hip_runtime.h>
 
 #include "lqt_internal.hpp"
@@ -40,53 +41,53 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 namespace blk64 {
 constexpr int N = 64, M = 32, NW = 4;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[10] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll",
-                                    "t64_fmat", "t64_fvec", "t64_tree", "t64_tanchor"};
+constexpr const char* kNames[11] = {"t64_prep", "t64_fold", "t64_chain", "t64_final", "t64_fchain", "t64_roll",
+                                    "t64_fmat", "t64_fvec", "t64_tree", "t64_tanchor", "t64_ftree"};
 #include "lqt_block.inc"
 }  // namespace blk64
 
 namespace blk32 {
 constexpr int N = 32, M = 32, NW = 2;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[10] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll",
-                                    "b32_fmat", "b32_fvec", "b32_tree", "b32_tanchor"};
+constexpr const char* kNames[11] = {"b32_prep", "b32_fold", "b32_chain", "b32_final", "b32_fchain", "b32_roll",
+                                    "b32_fmat", "b32_fvec", "b32_tree", "b32_tanchor", "b32_ftree"};
 #include "lqt_block.inc"
 }  // namespace blk32
 
 namespace blk32h {
 constexpr int N = 32, M = 16, NW = 2;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[10] = {"b32h_prep", "b32h_fold", "b32h_chain", "b32h_final", "b32h_fchain", "b32h_roll",
-                                   "b32h_fmat", "b32h_fvec", "b32h_tree", "b32h_tanchor"};
+constexpr const char* kNames[11] = {"b32h_prep", "b32h_fold", "b32h_chain", "b32h_final", "b32h_fchain", "b32h_roll",
+                                   "b32h_fmat", "b32h_fvec", "b32h_tree", "b32h_tanchor", "b32h_ftree"};
 #include "lqt_block.inc"
 }  // namespace blk32h
 
 namespace blk16 {
 constexpr int N = 16, M = 16, NW = 1;
 using CB = CstBT<N, M>;
-constexpr const char* kNames[10] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll",
-                                    "b16_fmat", "b16_fvec", "b16_tree", "b16_tanchor"};
+constexpr const char* kNames[11] = {"b16_prep", "b16_fold", "b16_chain", "b16_final", "b16_fchain", "b16_roll",
+                                    "b16_fmat", "b16_fvec", "b16_tree", "b16_tanchor", "b16_ftree"};
 #include "lqt_block.inc"
 }  // namespace blk16
 
-hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
-                       bool f32, hipStream_t s, const StageHook* h) {
+hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, int64_t tree_nc,
+                       bool want_fwd, bool f32, hipStream_t s, const StageHook* h) {
     switch (N) {
         case 64:
-            if (f32) blk64::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
-            else blk64::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            if (f32) blk64::run_block<float>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
+            else blk64::run_block<double>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
             break;
         case 32:
-            if (f32) blk32::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
-            else blk32::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            if (f32) blk32::run_block<float>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
+            else blk32::run_block<double>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
             break;
         case kEng32m16:
-            if (f32) blk32h::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
-            else blk32h::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            if (f32) blk32h::run_block<float>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
+            else blk32h::run_block<double>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
             break;
         case 16:
-            if (f32) blk16::run_block<float>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
-            else blk16::run_block<double>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+            if (f32) blk16::run_block<float>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
+            else blk16::run_block<double>(d_inst, ninst, nchunks, max_nc, tree_nc, want_fwd, s, h);
             break;
         default:
             return hipErrorInvalidValue;

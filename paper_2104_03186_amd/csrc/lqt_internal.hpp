@@ -67,6 +67,7 @@ struct GInst {
     int32_t eng;      // 0: wavefront engine; else padded dimension of the workgroup engine
     int32_t traj;     // 1: trajectory by forward prefixes (Method 2) into m2x, m2u (x, u are then null)
     void *m2x, *m2u;  // Method 2 states and controls (double)
+    int32_t tree;     // 1: chunk scans as trees (NC >= 2; workspace sized with the tree buffers)
 };
 
 size_t wave_lds_bytes(int nmax);
@@ -75,12 +76,13 @@ size_t wave_lds_bytes(int nmax);
 // with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
 int tile_class(int need);
 size_t tile_lds_bytes(int N);
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, bool f32,
+// tree_nc: the most chunks of an instance of the launch with tree set (0: none).
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h);
 // Workgroup engines (N = 16, 32, 64; time-invariant except c; class 64:
 // n, p, pT <= 64 and m <= 32).
-hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
-                       bool f32, hipStream_t s, const StageHook* h);
+hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, int64_t tree_nc,
+                       bool want_fwd, bool f32, hipStream_t s, const StageHook* h);
 // Trajectory by forward prefixes (Method 2) for the instances of a launch
 // group with traj set, after the group's backward pass (double S, v, K, d;
 // writes m2x, m2u); N = the group's size class (8, 16, 32, 64).

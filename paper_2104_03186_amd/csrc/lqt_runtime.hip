@@ -99,6 +99,24 @@ int wave_chunk(const lqt_routing& R, int64_t T, int div = 0, bool prefix = false
     return (int)std::max<int64_t>(16, std::min<int64_t>(int64_t(1) << 30, b));
 }
 
+// Chunk scans of a chunked-path instance with NC chunks as trees (GInst::tree):
+// the routing override tree (1: from two chunks on, 2: never), else from
+// kTreeMinNC chunks on.
+bool tree_for(const lqt_routing& R, int64_t NC) {
+    if (NC < 2 || R.tree == 2) return false;
+    return R.tree == 1 || NC >= lqt::kTreeMinNC;
+}
+
+// Chunk length of an instance whose chunks are scanned as trees on request
+// (routing tree = 1, for latency): about as many chunks as the size class's
+// tree kernels keep resident on the GPU at once, 8 to 64 steps each.  Short
+// chunks shorten the sequential fold and down-sweep inside every chunk; the
+// trees add only about log2 of the chunk count in dependent steps.
+int tree_chunk(int64_t T, int cls) {
+    const int64_t width = cls <= 8 ? 4096 : (cls <= 16 ? 2048 : (cls <= 32 ? 1024 : 256));
+    return (int)std::max<int64_t>(8, std::min<int64_t>(64, (T + width - 1) / width));
+}
+
 // Launch group of a chunked-path instance: size class (8, 16, 32, 64) and
 // engine (wavefront / workgroup), as an index 0..7.
 int group_key(const lqt_routing& R, const lqt_problem& p) {
@@ -312,8 +330,11 @@ Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool 
 }
 
 int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
-    return wave_chunk(plan->route, p.T, plan->tune_div[group_key(plan->route, p)],
-                      plan->desc.trajectory == LQT_TRAJ_PREFIX);
+    const int div = plan->tune_div[group_key(plan->route, p)];
+    const bool prefix = plan->desc.trajectory == LQT_TRAJ_PREFIX;
+    if (plan->route.tree == 1 && plan->route.wave_chunk == 0 && div <= 0 && !prefix)
+        return tree_chunk(p.T, tile_class_of(p));
+    return wave_chunk(plan->route, p.T, div, prefix);
 }
 
 // Workspace of one wavefront-path instance, and of its K, d scratch when the
@@ -321,7 +342,8 @@ int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
 size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
     const int B = chunk_for(plan, p);
     const int64_t NC = (p.T + B - 1) / B;
-    const int64_t wd = lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(plan->route, p), NC, B, p.c != nullptr);
+    const int64_t wd = lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(plan->route, p), NC, B, p.c != nullptr,
+                                       tree_for(plan->route, NC));
     return align_up((size_t)wd * sizeof(double));
 }
 // Scratch of one chunked-path instance beside its engine workspace: the
@@ -591,6 +613,7 @@ lqt::GInst make_ginst(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& 
     g.chunk0 = chunk0;
     g.ws = (double*)ws;
     g.eng = eng_of(plan->route, p);
+    g.tree = tree_for(plan->route, g.NC) ? 1 : 0;
     return g;
 }
 
@@ -771,11 +794,12 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     const bool gf32 = f32 && plan->desc.trajectory != LQT_TRAJ_PREFIX;
     for (size_t j0 = 0; j0 < wave.size();) {
         size_t j1 = j0;
-        int64_t nch = 0, max_nc = 0;
+        int64_t nch = 0, max_nc = 0, tree_nc = 0;
         bool fwd = false, m2 = false;
         while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
             nch += A.ginst_host[j1].NC;
             max_nc = std::max(max_nc, A.ginst_host[j1].NC);
+            if (A.ginst_host[j1].tree) tree_nc = std::max(tree_nc, A.ginst_host[j1].NC);
             fwd = fwd || want_fwd_c[j1] == 1;
             m2 = m2 || want_fwd_c[j1] == 2;
             ++j1;
@@ -783,8 +807,9 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         const lqt_problem& p0 = probs[wave[j0]];
         const int eng = eng_of(plan->route, p0);
         const lqt::StageHook* hk = plan->prof.on ? &hook : nullptr;
-        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, gf32, s, hk)
-                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, max_nc, fwd, gf32, s, hk);
+        hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, tree_nc, fwd, gf32, s, hk)
+                           : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, tree_nc, fwd, gf32, s,
+                                             hk);
         if (e == hipSuccess && m2)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, s,
                                 hk);
@@ -915,8 +940,8 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
         const bool fwd = gi.x || gi.u;
         const int eng = eng_of(plan->route, p);
         if (e == hipSuccess)
-            e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr)
-                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, gi.NC, fwd, f32, s, nullptr);
+            e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, gi.tree ? gi.NC : 0, fwd, f32, s, nullptr)
+                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, gi.tree ? gi.NC : 0, fwd, f32, s, nullptr);
         if (e == hipSuccess && gi.traj)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p), d_inst, 1, gi.NC, s, nullptr);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
@@ -1305,8 +1330,9 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
             const int64_t B = wave_chunk(p->route, desc->max_steps, 0, desc->trajectory == LQT_TRAJ_PREFIX);
             const int64_t NC = (desc->max_steps + B - 1) / B;
             const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
-            const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC),
-                                        lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC, B, false));
+            const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC, 0, true, true),
+                                        lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC, B, false,
+                                                        true));
             const size_t w = (size_t)wd * 8 +
                              (size_t)desc->max_steps * (desc->max_nu * desc->max_nx + desc->max_nu) * 8 + 4096;
             need = std::max(need, w);
@@ -1456,9 +1482,10 @@ lqt_status lqt_set_routing(lqt_plan_t plan, const lqt_routing* routing) {
     }
     const lqt_routing& r = *routing;
     if (r.path < 0 || r.path > 3 || r.block < 0 || r.block > 1 || r.lane_chunk < 0 || r.lane_chunk > 1024 ||
-        r.wave_chunk < 0 || r.wave_chunk > 4096)
-        return fail(plan, LQT_EINVAL, "lqt_set_routing: path=%d block=%d lane_chunk=%d wave_chunk=%d out of range",
-                    r.path, r.block, r.lane_chunk, r.wave_chunk);
+        r.wave_chunk < 0 || r.wave_chunk > 4096 || r.tree < 0 || r.tree > 2)
+        return fail(plan, LQT_EINVAL,
+                    "lqt_set_routing: path=%d block=%d lane_chunk=%d wave_chunk=%d tree=%d out of range", r.path,
+                    r.block, r.lane_chunk, r.wave_chunk, r.tree);
     plan->route = r;
     return LQT_OK;
 }

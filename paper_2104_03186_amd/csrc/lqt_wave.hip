@@ -780,7 +780,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const GInst& I = inst[ii];
-    if (ws_tree(I.NC)) return;  // t_tlevel + t_tanchor
+    if (I.tree) return;  // t_tlevel + t_tanchor
     const int lane = threadIdx.x;
     const int n = I.n;
     TSlots<N> s = tslots<N>(dyn);
@@ -825,8 +825,8 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     }
 }
 
-// Chunk scan as a tree for instances with at least kTreeMinNC chunks (as on
-// the workgroup engines): level l replaces element c by E_c (x) E_{c+2^l}
+// Chunk scan as a tree for instances with tree set (as on the workgroup
+// engines): level l replaces element c by E_c (x) E_{c+2^l}
 // with the general combination rule of Section IV-A; t_tanchor anchors the
 // suffixes on the terminal value (Section IV-B).  Records are n-dimensional.
 template <int N>
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(kW) void t_tlevel(const GInst* inst, int ninst, int
     if (gc >= nchunks) return;
     const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
-    if (!ws_tree(I.NC) || c == 0) return;  // the first chunk's element is never needed
+    if (!I.tree || c == 0) return;  // the first chunk's element is never needed
     const int lane = threadIdx.x;
     const int n = I.n;
     const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
@@ -909,7 +909,7 @@ __global__ __launch_bounds__(kW) void t_tanchor(const GInst* inst, int ninst, in
     if (gc >= nchunks) return;
     const GInst& I = inst[find_instance(inst, ninst, gc)];
     const int64_t c = gc - I.chunk0;
-    if (!ws_tree(I.NC)) return;
+    if (!I.tree) return;
     const int lane = threadIdx.x;
     const int n = I.n;
     const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
@@ -967,6 +967,7 @@ __global__ __launch_bounds__(kW) void t_fchain(const GInst* inst, int ninst) {
     const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const GInst& I = inst[ii];
+    if (I.tree) return;  // t_ftlevel
     const int lane = threadIdx.x;
     const int n = I.n;
     const int r = lane % N, g = lane / N;
@@ -1013,6 +1014,69 @@ __global__ __launch_bounds__(kW) void t_fchain(const GInst* inst, int ninst) {
                 wsync();
             }
         }
+    }
+}
+
+// State at every chunk start of an instance with tree set: the forward scan
+// over the chunk maps (Method 1 of Section IV-C) by recursive doubling.
+// Level l (d = 2^l) replaces map c by map_c o map_{c-d} where c >= d, so map
+// c becomes the composition of maps 0 .. c.  x_0 is folded into map 0 at
+// level 0; a map whose prefix reaches map 0 is then a constant (its value is
+// x_{c+1}) and only its vector is kept: after level l the maps c < 2^(l+1)
+// are constants.  Maps 0 .. NC-2 are scanned; the last level writes the
+// states at the chunk starts.  Records are n-dimensional, NC - 1 <= 2^levels.
+template <int N>
+__global__ __launch_bounds__(kW) void t_ftlevel(const GInst* inst, int ninst, int64_t nchunks, int level, int last) {
+    extern __shared__ __align__(16) double dyn[];
+    const int64_t gc = blockIdx.x;
+    if (gc >= nchunks) return;
+    const GInst& I = inst[find_instance(inst, ninst, gc)];
+    const int64_t c = gc - I.chunk0;
+    if (!I.tree || c > I.NC - 2) return;
+    const int lane = threadIdx.x;
+    const int n = I.n;
+    const int64_t nn = (int64_t)n * n, VD = val_doubles(n), ED = elem_doubles(n);
+    const InstWs ws = inst_ws(I);
+    const int64_t dist = int64_t(1) << level;
+    const double* src = level == 0 ? ws.map : ws.tree + ((level - 1) & 1) * I.NC * ED;
+    const double* mc = src + c * VD;
+    TSlots<N> s = tslots<N>(dyn);
+    double *P = s.m[0], *Q = s.m[1], *R = s.m[2];
+    double *xz = s.v[0], *yv = s.v[1];
+    // lane < n: row `lane` of (Phi v + phi) for the record rec (n x n, then n)
+    auto apply = [&](const double* rec, const double* v) {
+        double a = rec[nn + lane];
+        for (int j = 0; j < n; ++j) a = fma(rec[(int64_t)lane * n + j], v[j], a);
+        return a;
+    };
+    double o = 0.0;
+    if (level == 0 && c <= 1) {  // x_1 = Phi_0 x_0 + phi_0
+        if (lane < n) xz[lane] = I.x0[lane];
+        wsync();
+        if (lane < n) yv[lane] = apply(src, xz);
+        wsync();
+    } else if (c >= dist) {
+        if (lane < n) yv[lane] = src[(c - dist) * VD + nn + lane];
+        wsync();
+    }
+    if (c < dist) {  // carried over (a constant already)
+        if (lane < n) o = level == 0 ? yv[lane] : mc[nn + lane];
+    } else {
+        if (lane < n) o = apply(mc, yv);
+        if (c >= 2 * dist) {  // map_c o map_{c-d}: the matrix part
+            tload<N>(n, n, mc, n, P, lane);
+            tload<N>(n, n, src + (c - dist) * VD, n, Q, lane);
+            tgemm<N, false, false>(P, Q, R, 1.0, 0.0, lane);
+            tstore<N>(n, n, R, ws.tree + (level & 1) * I.NC * ED + c * VD, n, lane);
+        }
+    }
+    if (last) {
+        if (lane < n) {
+            ws.xs[(c + 1) * n + lane] = o;
+            if (c == 0) ws.xs[lane] = I.x0[lane];
+        }
+    } else if (lane < n) {
+        ws.tree[(level & 1) * I.NC * ED + c * VD + nn + lane] = o;
     }
 }
 
@@ -1230,22 +1294,22 @@ template <int N>
 struct TileNames;
 template <>
 struct TileNames<8> {
-    static constexpr const char* n[8] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll",
-                                          "t8_tree", "t8_tanchor"};
+    static constexpr const char* n[9] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll",
+                                          "t8_tree", "t8_tanchor", "t8_ftree"};
 };
 template <>
 struct TileNames<16> {
-    static constexpr const char* n[8] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll",
-                                          "t16_tree", "t16_tanchor"};
+    static constexpr const char* n[9] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll",
+                                          "t16_tree", "t16_tanchor", "t16_ftree"};
 };
 template <>
 struct TileNames<32> {
-    static constexpr const char* n[8] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll",
-                                          "t32_tree", "t32_tanchor"};
+    static constexpr const char* n[9] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll",
+                                          "t32_tree", "t32_tanchor", "t32_ftree"};
 };
 
 template <int N, typename OT>
-static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, hipStream_t s,
+static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, hipStream_t s,
                      const StageHook* h) {
     const char* const* nm = TileNames<N>::n;
     const size_t lds = tile_lds_bytes(N);
@@ -1254,7 +1318,7 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t ma
     if (!attr) {
         const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N, OT>,
                             (const void*)t_roll<N, OT>, (const void*)g_prep, (const void*)t_tlevel<N>,
-                            (const void*)t_tanchor<N>};
+                            (const void*)t_tanchor<N>, (const void*)t_ftlevel<N>};
         for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
@@ -1266,10 +1330,10 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t ma
         WStage st(h, nm[1], s);
         t_fold<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
-    if (max_nc >= kTreeMinNC) {
-        int levels = 0;
-        while ((int64_t(1) << levels) < max_nc - 1) ++levels;
-        {
+    int levels = 0;  // tree levels: 2^levels >= NC - 1 for every tree instance
+    while ((int64_t(1) << levels) < tree_nc - 1) ++levels;
+    if (tree_nc >= 2) {
+        if (levels > 0) {
             WStage st(h, nm[6], s);
             for (int l = 0; l < levels; ++l)
                 t_tlevel<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, l);
@@ -1286,6 +1350,12 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t ma
         t_final<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
     }
     if (want_fwd) {
+        if (tree_nc >= 2) {
+            const int fl = levels > 0 ? levels : 1;
+            WStage st(h, nm[8], s);
+            for (int l = 0; l < fl; ++l)
+                t_ftlevel<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, l, l == fl - 1);
+        }
         {
             WStage st(h, nm[4], s);
             t_fchain<N><<<ninst, kW, sizeof(double) * (1 + kW / N) * N, s>>>(d_inst, ninst);
@@ -1296,21 +1366,21 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t ma
 }
 
 template <typename OT>
-static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd,
+static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd,
                              hipStream_t s, const StageHook* h) {
     switch (N) {
-        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
-        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
-        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, max_nc, want_fwd, s, h); break;
+        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
+        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
+        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, bool want_fwd, bool f32,
+hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h) {
-    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, max_nc, want_fwd, s, h)
-               : tile_typed<double>(N, d_inst, ninst, nchunks, max_nc, want_fwd, s, h);
+    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h)
+               : tile_typed<double>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h);
 }
 
 }  // namespace lqt

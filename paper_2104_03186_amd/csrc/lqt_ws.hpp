@@ -94,22 +94,23 @@ __host__ __device__ inline bool ws_op_form(int eng, bool has_c) { return eng != 
 __host__ __device__ inline int64_t ws_ops_doubles(int d, int64_t B) { return (B > 1 ? B - 1 : 0) * 2 * (int64_t)d * d; }
 __host__ __device__ inline int64_t ws_opr_doubles(int d, int64_t B, int p) { return 2 * (int64_t)d * B * p; }
 
-// Value at the chunk starts of an instance with at least kTreeMinNC chunks
-// (either chunked engine): suffix products of the chunk elements by recursive
-// doubling (log2 NC levels, every chunk in parallel) instead of one walk over
-// the chunks; two more element buffers for the levels.
+// Chunk scans of an instance as trees (either chunked engine; GInst::tree):
+// the value at the chunk starts by recursive doubling over the chunk elements
+// and the state at the chunk starts by recursive doubling over the chunk maps
+// (about log2 NC levels, every chunk in parallel) instead of one walk over the
+// chunks.  The levels alternate between two element buffers.  By default an
+// instance takes the trees from kTreeMinNC chunks on.
 constexpr int64_t kTreeMinNC = 128;
-__host__ __device__ inline bool ws_tree(int64_t NC) { return NC >= kTreeMinNC; }
 
 // cst | agg[NC] (chunk elements; in the operator form agg[0] holds the common
 //     matrix part) | val[NC + 1] (value at chunk starts and T) | map[NC] (chunk
 //     affine maps) | xs[NC] (state at chunk starts) | ops | opr (operator form)
-//     | tree[2][NC] (chunk elements of the tree levels)
+//     | tree[2][NC] (chunk elements or chunk maps of the tree levels)
 __host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int64_t NC, int64_t B = 0,
-                                              bool has_c = true) {
+                                              bool has_c = true, bool tree_scan = false) {
     const int d = ws_dim(n, eng);
     const int64_t ops = ws_op_form(eng, has_c) ? ws_ops_doubles(d, B) + ws_opr_doubles(d, B, p) : 0;
-    const int64_t tree = ws_tree(NC) ? 2 * NC * elem_doubles(d) : 0;
+    const int64_t tree = tree_scan ? 2 * NC * elem_doubles(d) : 0;
     return ws_cst_doubles(n, m, p, eng) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
            NC * d + ops + tree + 32;
 }

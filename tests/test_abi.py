@@ -62,7 +62,7 @@ STRUCTS = {
     "lqt_fs_outputs": ("FSOutputs", ["V", "u", "x", "ux", "status"]),
     "lqt_plan_desc": ("PlanDesc", ["device", "max_nx", "max_nu", "prec", "hbm_budget_bytes", "max_steps",
                                    "max_inflight", "trajectory"]),
-    "lqt_routing": ("Routing", ["path", "block", "lane_chunk", "wave_chunk"]),
+    "lqt_routing": ("Routing", ["path", "block", "lane_chunk", "wave_chunk", "tree"]),
     "lqt_serve_stats": ("ServeStats", ["submitted", "completed", "batches", "queued", "running_batches",
                                        "max_running_batches", "max_batch", "pool_bytes", "pool_in_use",
                                        "pool_peak"]),

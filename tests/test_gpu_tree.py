@@ -1,15 +1,18 @@
-"""GPU parity of the chunk scan as a tree on the chunked engines: instances
-with at least 128 chunks form the value at every chunk start by recursive
+"""GPU parity of the chunk scans as trees on the chunked engines: instances
+with at least 128 chunks (or every instance of two chunks or more, with the
+routing override tree=True) form the value at every chunk start by recursive
 doubling over their chunk elements (the parallel scan of Section II-C with
 the general combination rule of Section IV-A, anchored on the terminal value
-of Section IV-B) instead of walking the chunks in sequence.  Checked against
-the FP64 oracle: every workgroup class (16, 32 in both control widths, 64)
-and every wavefront class (8, 16, 32; time-varying data), the operator-form
-fold and the per-chunk fold (offsets c), chunk counts around the tree's
-level boundaries, MIXED, the generalised cost, forward prefixes (Method 2,
+of Section IV-B) and the state at every chunk start by recursive doubling
+over the chunk maps (Method 1 of Section IV-C), instead of walking the
+chunks in sequence.  Checked against the FP64 oracle: every workgroup class
+(16, 32 in both control widths, 64) and every wavefront class (8, 16, 32;
+time-varying data), the operator-form fold and the per-chunk fold (offsets
+c), chunk counts around the trees' level boundaries (2, 3, 5, 17, 33, 128,
+129, 257 chunks), MIXED, the generalised cost, forward prefixes (Method 2,
 which reads the untouched chunk elements), the default chunking of long
-instances, and a batch of tree and chain instances equal to each instance
-alone, bit for bit.
+instances, the override tree=False on a long instance, and a batch of tree
+and chain instances equal to each instance alone, bit for bit.
 
 Tolerance: tests/helpers.err (stacked and per step), 1e-10 (FP64), 1e-5
 (MIXED).
@@ -43,12 +46,12 @@ def api():
     return _api
 
 
-def solve(api, probs, prec="fp64", chunk=16, trajectory="maps"):
+def solve(api, probs, prec="fp64", chunk=16, trajectory="maps", tree=None):
     import torch
 
     plan = api.Plan(64, 32, prec=prec, device=0, trajectory=trajectory)
     try:
-        plan.set_routing(wave_chunk=chunk)
+        plan.set_routing(wave_chunk=chunk, tree=tree)
         dt = torch.float64 if prec == "fp64" else torch.float32
         dps = [api.DeviceProblem(p) for p in probs]
         dos = [api.DeviceOutputs(p.n, p.m, p.T, dtype=dt) for p in probs]
@@ -150,3 +153,62 @@ def test_status_codes_and_isolation(api):
     res = solve(api, [good, bad, nan])
     assert [st for st, _ in res] == [0, 3, 4]
     check(res[0][1], oracle.solve(good), TOL["fp64"])
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("T", [16 + 3, 16 * 2 + 1, 16 * 4 + 7, 16 * 17, 16 * 32 + 9])
+def test_forced_trees_few_chunks(api, name, T):
+    """tree=True: 2, 3, 5, 17 and 33 chunks (one or two levels past a power
+    of two, both trees with a ragged last chunk)."""
+    prob = SHAPES[name](T)
+    _say("forced trees", name, "T=", T, "chunk 16")
+    ((st, got),) = solve(api, [prob], tree=True)
+    assert st == 0
+    check(got, oracle.solve(prob), TOL["fp64"])
+
+
+@pytest.mark.parametrize("name", ["class16_offsets", "class64", "wave8", "wave32_varying"])
+def test_forced_trees_mixed(api, name):
+    prob = SHAPES[name](16 * 37 + 5)
+    _say("forced trees mixed", name)
+    ((st, got),) = solve(api, [prob], prec="mixed", tree=True)
+    assert st == 0
+    check(got, oracle.solve(prob), TOL["mixed"])
+
+
+@pytest.mark.parametrize("name", ["class16", "class32_m16", "wave16_varying"])
+def test_forced_trees_default_chunking(api, name):
+    """tree=True with the default chunk length (T = 1000 and 5000)."""
+    for T in (1000, 5000):
+        prob = SHAPES[name](T)
+        _say("forced trees default chunking", name, "T=", T)
+        ((st, got),) = solve(api, [prob], chunk=0, tree=True)
+        assert st == 0
+        check(got, oracle.solve(prob), TOL["fp64"])
+
+
+@pytest.mark.parametrize("name", ["class16", "wave8"])
+def test_trees_off_long_instance(api, name):
+    """tree=False: 200 chunks walked in sequence."""
+    prob = SHAPES[name](16 * 200)
+    _say("trees off", name)
+    ((st, got),) = solve(api, [prob], tree=False)
+    assert st == 0
+    check(got, oracle.solve(prob), TOL["fp64"])
+
+
+def test_forced_trees_batch_with_one_chunk_instances(api):
+    """tree=True in a batch whose instances have 1 to 40 chunks (an instance
+    of one chunk has nothing to scan and keeps the walks): each equals the
+    instance alone, bit for bit, and the oracle."""
+    probs = [SHAPES["class16"](10), SHAPES["class16"](16 * 40), SHAPES["class16"](16 * 3 - 2),
+             SHAPES["wave8"](16), SHAPES["wave8"](16 * 21 + 1), SHAPES["class64"](16 * 9 + 4),
+             SHAPES["class64"](7)]
+    _say("forced trees, batch with one-chunk instances")
+    mix = solve(api, probs, tree=True)
+    for i, p in enumerate(probs):
+        (alone,) = solve(api, [p], tree=True)
+        assert mix[i][0] == 0 and alone[0] == 0, i
+        for f in FAMILIES:
+            assert np.array_equal(mix[i][1][f], alone[1][f]), (i, f)
+        check(mix[i][1], oracle.solve(p), TOL["fp64"])
