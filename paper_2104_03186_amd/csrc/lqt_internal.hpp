@@ -75,7 +75,6 @@ size_t wave_lds_bytes(int nmax);
 // Size-class variant of the wavefront pipeline: matrices zero-padded to N x N
 // with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
 int tile_class(int need);
-size_t tile_lds_bytes(int N);
 // tree_nc: the most chunks of an instance of the launch with tree set (0: none).
 hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, bool f32,
                       hipStream_t s, const StageHook* h);

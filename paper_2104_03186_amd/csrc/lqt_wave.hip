@@ -496,9 +496,75 @@ WDI void ttrsm_m(const double* R, double* B, double* x, int m, int lane) {
     wsync();
 }
 
-// Mi = M^{-1}, Gauss-Jordan with partial pivoting (M destroyed).
+WDI double rlane64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Mi = M^{-1} for N <= 16, Gauss-Jordan with partial pivoting in registers:
+// lane r < N keeps row r of [M | I]; a column's pivot is the largest
+// magnitude among the rows not yet pivots (wavefront reduction), the pivot
+// row is read lane to lane by the whole wavefront and every other row is
+// eliminated in place.  Rows are not exchanged: row c of the inverse is the
+// identity part of the c-th pivot row.  No LDS traffic and no wavefront
+// ordering inside the elimination.
+template <int N>
+WDI void tinv_reg(const double* Mm, double* Mi, int lane) {
+    constexpr int ld = TL<N>::ld;
+    const int r = lane;
+    const bool act = r < N;
+    double a[2 * N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        a[j] = act ? Mm[r * ld + j] : 0.0;
+        a[N + j] = (act && r == j) ? 1.0 : 0.0;
+    }
+    bool used = !act;
+    int ci = 0;  // this row's place in the pivot order
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double best = used ? -1.0 : fabs(a[k]);
+        int bi = r;
+#pragma unroll
+        for (int off = kW / 2; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, kW);
+            const int oi = __shfl_xor(bi, off, kW);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        const int p = __builtin_amdgcn_readfirstlane(bi);
+        const double inv = 1.0 / rlane64(a[k], p);
+        const bool me = r == p;
+        const double f = me ? 0.0 : a[k] * inv;
+        // columns before k are unit vectors already (zero in the pivot row)
+#pragma unroll
+        for (int j = k + 1; j < 2 * N; ++j) {
+            const double pj = rlane64(a[j], p);
+            a[j] = me ? pj * inv : fma(-f, pj, a[j]);
+        }
+        a[k] = me ? 1.0 : 0.0;
+        if (me) ci = k;
+        used = used || me;
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) Mi[ci * ld + j] = a[N + j];
+    }
+    wsync();
+}
+
+// Mi = M^{-1}, Gauss-Jordan with partial pivoting (M destroyed): the register
+// form up to N = 16, else in LDS with explicit row exchanges.
 template <int N>
 WDI void tinv(double* Mm, double* Mi, int lane) {
+    if constexpr (N <= 16) {
+        tinv_reg<N>(Mm, Mi, lane);
+        return;
+    }
     constexpr int ld = TL<N>::ld;
     for (int idx = lane; idx < N * N; idx += kW) {
         const int r = idx / N, q = idx % N;
@@ -574,22 +640,36 @@ WDI void tstore(int R, int Q, const double* l, OT* g, int gq, int lane) {
     }
 }
 
-template <int N>
+// LDS of a class-N kernel: NM matrix slots, then NV vector slots.  Each
+// kernel takes only the slots it uses (and is launched with that much LDS),
+// so the kernels with few slots keep more wavefronts resident.
+template <int N, int NM = 14, int NV = 12>
 struct TSlots {
-    double* m[14];
-    double* v[12];
-    static constexpr int doubles() { return 14 * TL<N>::mat + 12 * (N + 2); }
+    double* m[NM];
+    double* v[NV];
+    static constexpr int NMv = NM, NVv = NV;
+    static constexpr int doubles() { return NM * TL<N>::mat + NV * (N + 2); }
+    static constexpr size_t bytes() { return sizeof(double) * doubles(); }
 };
 
-template <int N>
-WDI TSlots<N> tslots(double* base) {
-    TSlots<N> s;
+template <int N, int NM = 14, int NV = 12>
+WDI TSlots<N, NM, NV> tslots(double* base) {
+    TSlots<N, NM, NV> s;
 #pragma unroll
-    for (int i = 0; i < 14; ++i) s.m[i] = base + i * TL<N>::mat;
+    for (int i = 0; i < NM; ++i) s.m[i] = base + i * TL<N>::mat;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) s.v[i] = base + 14 * TL<N>::mat + i * (N + 2);
+    for (int i = 0; i < NV; ++i) s.v[i] = base + NM * TL<N>::mat + i * (N + 2);
     return s;
 }
+
+// Slots of each kernel: fold, chain and anchor, tree level, down-sweep,
+// forward tree level, roll-out.
+template <int N> using FoldSlots = TSlots<N, 12, 10>;
+template <int N> using ChainSlots = TSlots<N, 8, 5>;
+template <int N> using LevelSlots = TSlots<N, 12, 9>;
+template <int N> using FinalSlots = TSlots<N, 14, 11>;
+template <int N> using FLevelSlots = TSlots<N, 3, 2>;
+template <int N> using RollSlots = TSlots<N, 2, 4>;
 
 // eta_k = W r_k (W = H^T X in LDS, n x p zero padded, p <= N).
 template <int N>
@@ -658,7 +738,7 @@ WDI void tvec_load(int n, const double* g, double* l, int lane) {
 // the symmetric updates are products of a factor with itself.
 template <int N>
 WDI void t_step_combine(int m, const double* F, const double* c, const double* G, const double* ek,
-                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, TSlots<N>& s,
+                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, FoldSlots<N>& s,
                         int lane) {
     double* Z = s.m[7];
     double* Rf = s.m[8];
@@ -719,7 +799,7 @@ __global__ __launch_bounds__(kW) void t_fold(const GInst* inst, int ninst, int64
     if (c == 0) return;
     const int lane = threadIdx.x;
     const int n = I.n, m = I.m, p = I.p;
-    TSlots<N> s = tslots<N>(dyn);
+    FoldSlots<N> s = tslots<N, FoldSlots<N>::NMv, FoldSlots<N>::NVv>(dyn);
     const InstWs ws = inst_ws(I);
     const CstW cl = cst_layout(n, m, p);
     const int64_t k0 = c * I.B;
@@ -783,7 +863,7 @@ __global__ __launch_bounds__(kW) void t_chain(const GInst* inst, int ninst) {
     if (I.tree) return;  // t_tlevel + t_tanchor
     const int lane = threadIdx.x;
     const int n = I.n;
-    TSlots<N> s = tslots<N>(dyn);
+    ChainSlots<N> s = tslots<N, ChainSlots<N>::NMv, ChainSlots<N>::NVv>(dyn);
     const InstWs ws = inst_ws(I);
     const CstW cl = cst_layout(n, I.m, I.p);
     const int64_t nn = (int64_t)n * n;
@@ -851,7 +931,7 @@ __global__ __launch_bounds__(kW) void t_tlevel(const GInst* inst, int ninst, int
         return;
     }
     const double* ey = src + (c + dist) * ED;
-    TSlots<N> s = tslots<N>(dyn);
+    LevelSlots<N> s = tslots<N, LevelSlots<N>::NMv, LevelSlots<N>::NVv>(dyn);
     double *XA = s.m[0], *XC = s.m[1], *XJ = s.m[2], *YA = s.m[3], *YC = s.m[4], *YJ = s.m[5];
     double *Mm = s.m[6], *Mi = s.m[7], *T1 = s.m[8], *U1 = s.m[9], *W1 = s.m[10], *R1 = s.m[11];
     double *xb = s.v[0], *xe = s.v[1], *yb = s.v[2], *ye = s.v[3], *y0 = s.v[4], *z = s.v[5], *w = s.v[6];
@@ -922,7 +1002,7 @@ __global__ __launch_bounds__(kW) void t_tanchor(const GInst* inst, int ninst, in
         return;
     }
     const double* e = (levels > 0 ? ws.tree + ((levels - 1) & 1) * I.NC * ED : ws.agg) + c * ED;
-    TSlots<N> s = tslots<N>(dyn);
+    ChainSlots<N> s = tslots<N, ChainSlots<N>::NMv, ChainSlots<N>::NVv>(dyn);
     double *EA = s.m[0], *EC = s.m[1], *EJ = s.m[2], *Sm = s.m[3];
     double *Mm = s.m[4], *Mi = s.m[5], *T1 = s.m[6], *P = s.m[7];
     double *Eb = s.v[0], *Ee = s.v[1], *v = s.v[2], *t = s.v[3], *nv = s.v[4];
@@ -1040,7 +1120,7 @@ __global__ __launch_bounds__(kW) void t_ftlevel(const GInst* inst, int ninst, in
     const int64_t dist = int64_t(1) << level;
     const double* src = level == 0 ? ws.map : ws.tree + ((level - 1) & 1) * I.NC * ED;
     const double* mc = src + c * VD;
-    TSlots<N> s = tslots<N>(dyn);
+    FLevelSlots<N> s = tslots<N, FLevelSlots<N>::NMv, FLevelSlots<N>::NVv>(dyn);
     double *P = s.m[0], *Q = s.m[1], *R = s.m[2];
     double *xz = s.v[0], *yv = s.v[1];
     // lane < n: row `lane` of (Phi v + phi) for the record rec (n x n, then n)
@@ -1090,7 +1170,7 @@ __global__ __launch_bounds__(kW) void t_final(const GInst* inst, int ninst, int6
     const int64_t c = gc - I.chunk0;
     const int lane = threadIdx.x;
     const int n = I.n, m = I.m, p = I.p;
-    TSlots<N> s = tslots<N>(dyn);
+    FinalSlots<N> s = tslots<N, FinalSlots<N>::NMv, FinalSlots<N>::NVv>(dyn);
     const InstWs ws = inst_ws(I);
     const CstW cl = cst_layout(n, m, p);
     const int64_t nn = (int64_t)n * n;
@@ -1205,7 +1285,7 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
     const int64_t c = gc - I.chunk0;
     const int lane = threadIdx.x;
     const int n = I.n, m = I.m;
-    TSlots<N> s = tslots<N>(dyn);
+    RollSlots<N> s = tslots<N, RollSlots<N>::NMv, RollSlots<N>::NVv>(dyn);
     const InstWs ws = inst_ws(I);
     const uint32_t ps = I.per_step;
     const int64_t k0 = c * I.B;
@@ -1281,14 +1361,6 @@ int tile_class(int need) {
     return 0;
 }
 
-size_t tile_lds_bytes(int N) {
-    switch (N) {
-        case 8: return TSlots<8>::doubles() * sizeof(double);
-        case 16: return TSlots<16>::doubles() * sizeof(double);
-        case 32: return TSlots<32>::doubles() * sizeof(double);
-    }
-    return 0;
-}
 
 template <int N>
 struct TileNames;
@@ -1312,7 +1384,6 @@ template <int N, typename OT>
 static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, hipStream_t s,
                      const StageHook* h) {
     const char* const* nm = TileNames<N>::n;
-    const size_t lds = tile_lds_bytes(N);
     const size_t glds = wave_lds_bytes(N);
     static bool attr = false;
     if (!attr) {
@@ -1328,7 +1399,7 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tr
     }
     {
         WStage st(h, nm[1], s);
-        t_fold<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+        t_fold<N><<<(unsigned)nchunks, kW, FoldSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks);
     }
     int levels = 0;  // tree levels: 2^levels >= NC - 1 for every tree instance
     while ((int64_t(1) << levels) < tree_nc - 1) ++levels;
@@ -1336,32 +1407,32 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tr
         if (levels > 0) {
             WStage st(h, nm[6], s);
             for (int l = 0; l < levels; ++l)
-                t_tlevel<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, l);
+                t_tlevel<N><<<(unsigned)nchunks, kW, LevelSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks, l);
         }
         WStage st(h, nm[7], s);
-        t_tanchor<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, levels);
+        t_tanchor<N><<<(unsigned)nchunks, kW, ChainSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks, levels);
     }
     {
         WStage st(h, nm[2], s);
-        t_chain<N><<<ninst, kW, lds, s>>>(d_inst, ninst);
+        t_chain<N><<<ninst, kW, ChainSlots<N>::bytes(), s>>>(d_inst, ninst);
     }
     {
         WStage st(h, nm[3], s);
-        t_final<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+        t_final<N, OT><<<(unsigned)nchunks, kW, FinalSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks);
     }
     if (want_fwd) {
         if (tree_nc >= 2) {
             const int fl = levels > 0 ? levels : 1;
             WStage st(h, nm[8], s);
             for (int l = 0; l < fl; ++l)
-                t_ftlevel<N><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks, l, l == fl - 1);
+                t_ftlevel<N><<<(unsigned)nchunks, kW, FLevelSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks, l, l == fl - 1);
         }
         {
             WStage st(h, nm[4], s);
             t_fchain<N><<<ninst, kW, sizeof(double) * (1 + kW / N) * N, s>>>(d_inst, ninst);
         }
         WStage st(h, nm[5], s);
-        t_roll<N, OT><<<(unsigned)nchunks, kW, lds, s>>>(d_inst, ninst, nchunks);
+        t_roll<N, OT><<<(unsigned)nchunks, kW, RollSlots<N>::bytes(), s>>>(d_inst, ninst, nchunks);
     }
 }
 
