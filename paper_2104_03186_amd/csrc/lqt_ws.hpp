@@ -51,7 +51,8 @@ struct CstBT {
     static constexpr int64_t W = J + N * N;
     static constexpr int64_t ST = W + N * N;
     static constexpr int64_t VT = ST + N * N;
-    static constexpr int64_t end = VT + N;
+    static constexpr int64_t WT = VT + N;  // W transposed (coalesced reads of W r by lanes over W's rows)
+    static constexpr int64_t end = WT + N * N;
 };
 
 // Engine of an instance: 0 = wavefront engine (records of dimension n), or
