@@ -212,3 +212,32 @@ def test_forced_trees_batch_with_one_chunk_instances(api):
         for f in FAMILIES:
             assert np.array_equal(mix[i][1][f], alone[1][f]), (i, f)
         check(mix[i][1], oracle.solve(p), TOL["fp64"])
+
+
+def test_routing_tree_field_validation(api):
+    """lqt_set_routing rejects tree values outside 0..2 with LQT_EINVAL and
+    leaves the plan's routing as it was."""
+    import ctypes
+
+    from paper_2104_03186_amd import _lib
+
+    plan = api.Plan(16, 8)
+    try:
+        plan.set_routing(tree=True)
+        for bad in (-1, 3):
+            r = _lib.Routing(tree=bad)
+            rc = _lib.load().lqt_set_routing(plan.handle, ctypes.byref(r))
+            assert rc == _lib.EINVAL, bad
+            assert "tree" in _lib.last_error(plan.handle)
+        prob = SHAPES["class16"](16 * 9 + 3)
+        _say("routing after rejected tree values")
+        dp = api.DeviceProblem(prob)
+        do = api.DeviceOutputs(prob.n, prob.m, prob.T)
+        plan.solve([dp], [do])
+        import torch
+
+        torch.cuda.synchronize()
+        assert int(do.status.item()) == 0
+        check(do.host(), oracle.solve(prob), TOL["fp64"])
+    finally:
+        plan.close()

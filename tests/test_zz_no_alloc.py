@@ -4,8 +4,9 @@ Two calls in a row on one plan through the C ABI, the second with a smaller
 instance, each compared with lqt_solve of the same instance (the same
 kernels and chunking: equal bit for bit) and with the oracle (the FP64 gate
 of the parity tests); a generalised-cost instance, a wavefront-engine
-instance, a long instance whose chunk elements are scanned as a tree and a
-MIXED plan; the size limit of the static workspace.
+instance, a long instance whose chunk elements are scanned as a tree, both
+chunked engines with the chunk scans as trees by request, and a MIXED plan;
+the size limit of the static workspace.
 """
 import sys
 
@@ -89,6 +90,22 @@ def test_generalised_and_workgroup_engine(api):
                      inputs.diag_problem(12, 6, 20000, 2, 6),  # 313 chunks: scanned as a tree
                      inputs.generalised_problem(12, 5, 700, seed=22, p=8, per_step=2)):
             _say("noalloc", prob.n, prob.m, prob.T)
+            got, alone = both(api, plan, prob, torch.float64)
+            check(got, alone, oracle.solve(prob), TOL["fp64"])
+    finally:
+        plan.close()
+
+
+def test_forced_trees(api):
+    """Routing tree=True: the chunk scans of both chunked engines as trees,
+    the same with and without allocation."""
+    import torch
+
+    plan = api.Plan(16, 8, prec="fp64")
+    try:
+        plan.set_routing(tree=True)
+        for prob in (inputs.diag_problem(16, 8, 2000, 2, 7), inputs.random_problem(6, 3, 3001, seed=13)):
+            _say("noalloc with trees", prob.n, prob.m, prob.T)
             got, alone = both(api, plan, prob, torch.float64)
             check(got, alone, oracle.solve(prob), TOL["fp64"])
     finally:
