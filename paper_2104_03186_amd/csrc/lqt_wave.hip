@@ -233,7 +233,9 @@ __global__ __launch_bounds__(kW) void g_prep(const GInst* inst, int ninst, int N
 
 template <int N>
 struct TL {
-    static constexpr int ld = N + 2;   // 16-byte aligned rows, rows spread over the banks
+    // 16-byte aligned rows, rows spread over the banks; class 8 unpadded (a
+    // smaller LDS footprint keeps more wavefronts resident)
+    static constexpr int ld = N == 8 ? 8 : N + 2;
     static constexpr int mat = N * ld;
     static constexpr int T = N / 8;    // per-lane output tile is T x T
 };
