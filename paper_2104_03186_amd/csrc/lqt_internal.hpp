@@ -68,6 +68,7 @@ struct GInst {
     int32_t traj;     // 1: trajectory by forward prefixes (Method 2) into m2x, m2u (x, u are then null)
     void *m2x, *m2u;  // Method 2 states and controls (double)
     int32_t tree;     // 1: chunk scans as trees (NC >= 2; workspace sized with the tree buffers)
+    int32_t opf;      // 1: wavefront-engine fold in operator form (class 8, time-invariant, no c, maps)
 };
 
 size_t wave_lds_bytes(int nmax);
@@ -76,8 +77,9 @@ size_t wave_lds_bytes(int nmax);
 // with N = tile_class(max(n, m, p)) in {8, 16, 32} (0: no class).
 int tile_class(int need);
 // tree_nc: the most chunks of an instance of the launch with tree set (0: none).
+// opf_any: some instance of the launch has opf set.
 hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, bool f32,
-                      hipStream_t s, const StageHook* h);
+                      hipStream_t s, const StageHook* h, bool opf_any = false);
 // Workgroup engines (N = 16, 32, 64; time-invariant except c; class 64:
 // n, p, pT <= 64 and m <= 32).
 hipError_t block_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t max_nc, int64_t tree_nc,

@@ -329,6 +329,15 @@ Layout layout_for(const lqt_routing& R, const lqt_problem& p, bool need_K, bool 
     return L;
 }
 
+// Wavefront-engine fold in operator form (GInst::opf): class 8 on the
+// wavefront engine, time-invariant (only r per step), no offsets c,
+// trajectory by maps, at least two chunks of at least two steps.
+bool opf_for(lqt_plan_t plan, const lqt_problem& p, int64_t B, int64_t NC) {
+    return eng_of(plan->route, p) == 0 && tile_class_of(p) == 8 && p.c == nullptr &&
+           (p.per_step & (LQT_PS_F | LQT_PS_L | LQT_PS_U | LQT_PS_H | LQT_PS_X)) == 0 &&
+           plan->desc.trajectory != LQT_TRAJ_PREFIX && NC >= 2 && B >= 2;
+}
+
 int chunk_for(lqt_plan_t plan, const lqt_problem& p) {
     const int div = plan->tune_div[group_key(plan->route, p)];
     const bool prefix = plan->desc.trajectory == LQT_TRAJ_PREFIX;
@@ -343,7 +352,7 @@ size_t wave_bytes(lqt_plan_t plan, const lqt_problem& p) {
     const int B = chunk_for(plan, p);
     const int64_t NC = (p.T + B - 1) / B;
     const int64_t wd = lqt::ws_doubles(p.nx, p.nu, p.ny, eng_of(plan->route, p), NC, B, p.c != nullptr,
-                                       tree_for(plan->route, NC));
+                                       tree_for(plan->route, NC), opf_for(plan, p, B, NC));
     return align_up((size_t)wd * sizeof(double));
 }
 // Scratch of one chunked-path instance beside its engine workspace: the
@@ -614,6 +623,7 @@ lqt::GInst make_ginst(lqt_plan_t plan, const lqt_problem& p, const lqt_outputs& 
     g.ws = (double*)ws;
     g.eng = eng_of(plan->route, p);
     g.tree = tree_for(plan->route, g.NC) ? 1 : 0;
+    g.opf = opf_for(plan, p, g.B, g.NC) ? 1 : 0;
     return g;
 }
 
@@ -795,11 +805,12 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
     for (size_t j0 = 0; j0 < wave.size();) {
         size_t j1 = j0;
         int64_t nch = 0, max_nc = 0, tree_nc = 0;
-        bool fwd = false, m2 = false;
+        bool fwd = false, m2 = false, opf_any = false;
         while (j1 < wave.size() && cls(wave[j1]) == cls(wave[j0])) {
             nch += A.ginst_host[j1].NC;
             max_nc = std::max(max_nc, A.ginst_host[j1].NC);
             if (A.ginst_host[j1].tree) tree_nc = std::max(tree_nc, A.ginst_host[j1].NC);
+            opf_any = opf_any || A.ginst_host[j1].opf;
             fwd = fwd || want_fwd_c[j1] == 1;
             m2 = m2 || want_fwd_c[j1] == 2;
             ++j1;
@@ -809,7 +820,7 @@ lqt_status solve_all(lqt_plan_t plan, Arena& A, const lqt_problem* probs, const 
         const lqt::StageHook* hk = plan->prof.on ? &hook : nullptr;
         hipError_t e = eng ? lqt::block_solve(eng, d_inst + j0, (int)(j1 - j0), nch, max_nc, tree_nc, fwd, gf32, s, hk)
                            : lqt::tile_solve(tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, tree_nc, fwd, gf32, s,
-                                             hk);
+                                             hk, opf_any);
         if (e == hipSuccess && m2)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p0), d_inst + j0, (int)(j1 - j0), nch, s,
                                 hk);
@@ -941,7 +952,8 @@ lqt_status solve_static(lqt_plan_t plan, char* base, size_t cap, const lqt_probl
         const int eng = eng_of(plan->route, p);
         if (e == hipSuccess)
             e = eng ? lqt::block_solve(eng, d_inst, 1, gi.NC, gi.NC, gi.tree ? gi.NC : 0, fwd, f32, s, nullptr)
-                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, gi.tree ? gi.NC : 0, fwd, f32, s, nullptr);
+                    : lqt::tile_solve(tile_class_of(p), d_inst, 1, gi.NC, gi.tree ? gi.NC : 0, fwd, f32, s, nullptr,
+                                      gi.opf != 0);
         if (e == hipSuccess && gi.traj)
             e = lqt::m2_chunked(eng ? lqt::eng_dim(eng) : tile_class_of(p), d_inst, 1, gi.NC, s, nullptr);
         if (e != hipSuccess) return fail(plan, LQT_EHIP, "wavefront-path launch failed: %s", hipGetErrorString(e));
@@ -1330,7 +1342,8 @@ lqt_status lqt_plan(const lqt_plan_desc* desc, lqt_plan_t* out) {
             const int64_t B = wave_chunk(p->route, desc->max_steps, 0, desc->trajectory == LQT_TRAJ_PREFIX);
             const int64_t NC = (desc->max_steps + B - 1) / B;
             const int cls = lqt::tile_class(std::max(desc->max_nx, desc->max_nu));
-            const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC, 0, true, true),
+            const int64_t wd = std::max(lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, 0, NC, B, false, true,
+                                                        true),
                                         lqt::ws_doubles(desc->max_nx, desc->max_nu, desc->max_nx, cls, NC, B, false,
                                                         true));
             const size_t w = (size_t)wd * 8 +

@@ -672,6 +672,7 @@ template <int N> using LevelSlots = TSlots<N, 12, 9>;
 template <int N> using FinalSlots = TSlots<N, 14, 11>;
 template <int N> using FLevelSlots = TSlots<N, 3, 2>;
 template <int N> using RollSlots = TSlots<N, 2, 4>;
+template <int N> using FmatSlots = TSlots<N, 15, 10>;  // operator-form matrix fold
 
 // eta_k = W r_k (W = H^T X in LDS, n x p zero padded, p <= N).
 template <int N>
@@ -738,10 +739,14 @@ WDI void tvec_load(int n, const double* g, double* l, int lane) {
 //   J' = F^T (J_P - V^T V) F + J_k.
 // Every inverse is applied as triangular solves with the Cholesky factor, and
 // the symmetric updates are products of a factor with itself.
-template <int N>
+// With opE (slots with at least 15 matrices), also stores the operators of
+// the vector part for c = 0: eta' = E eta_P + eta_k and b' = b_P + B^ eta_P,
+// E = F^T (I - V^T R^{-1} G^T) at opE and B^ = Q R^{-1} G^T after it (n x n
+// each, row-major).
+template <int N, typename SL>
 WDI void t_step_combine(int m, const double* F, const double* c, const double* G, const double* ek,
-                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, FoldSlots<N>& s,
-                        int lane) {
+                        const double* Js, double* PA, double* Pb, double* PC, double* Pe, double* PJ, SL& s,
+                        int lane, int n = 0, double* opE = nullptr) {
     double* Z = s.m[7];
     double* Rf = s.m[8];
     double* VF = s.m[9];
@@ -760,6 +765,26 @@ WDI void t_step_combine(int m, const double* F, const double* c, const double* G
     ttrsm_m<N, false>(Rf, Z, y, m, lane);
     tgemm<N, true, true>(G, PA, Qt, 1.0, 0.0, lane);               // (A_P G)^T
     ttrsm_m<N, false>(Rf, Qt, nullptr, m, lane);                   // Q^T = R^{-1} (A_P G)^T
+    if constexpr (SL::NMv >= 15) {
+        if (opE) {
+            double *Gt = s.m[12], *Tm = s.m[13], *Em = s.m[14];
+            for (int idx = lane; idx < N * N; idx += kW) {  // G^T
+                const int a = idx / N, j = idx % N;
+                Gt[a * ld + j] = G[j * ld + a];
+            }
+            wsync();
+            ttrsm_m<N, false>(Rf, Gt, nullptr, m, lane);          // R^{-1} G^T
+            tgemm<N, true, false>(Z, Gt, Tm, -1.0, 0.0, lane);    // -V^T R^{-1} G^T
+            if (lane < N) Tm[lane * ld + lane] += 1.0;
+            wsync();
+            tgemm<N, true, false>(F, Tm, Em, 1.0, 0.0, lane);     // E
+            tstore<N>(n, n, Em, opE, n, lane);
+            wsync();
+            tgemm<N, true, false>(Qt, Gt, Em, 1.0, 0.0, lane);    // B^
+            tstore<N>(n, n, Em, opE + (int64_t)n * n, n, lane);
+            wsync();
+        }
+    }
     // b' = A_P c + Q y + b_P
     tgemv<N, false>(PA, c, nb, 1.0, 0.0, lane);
     tgemv<N, true>(Qt, y, nb, 1.0, 1.0, lane);
@@ -789,6 +814,125 @@ WDI void t_step_combine(int m, const double* F, const double* c, const double* G
     wsync();
 }
 
+// Operator form of the fold for instances with opf set (class 8,
+// time-invariant, no offsets c, trajectory by maps): every chunk but the last
+// has the full length B and the same matrix part (A, C, J), so one wavefront
+// per instance folds one full chunk's B steps once, storing for each relative
+// step j (counted from the chunk's end) the operators of the vector part
+// (t_step_combine with opE), and writes the matrix part to chunk 0's element
+// slot (chunk 0's element is never needed).  t_fold then runs only the vector
+// recursion per chunk.
+template <int N>
+__global__ __launch_bounds__(kW) void t_fmat(const GInst* inst, int ninst) {
+    extern __shared__ __align__(16) double dyn[];
+    const int ii = blockIdx.x;
+    if (ii >= ninst) return;
+    const GInst& I = inst[ii];
+    if (!I.opf) return;
+    const int lane = threadIdx.x;
+    const int n = I.n, m = I.m, p = I.p;
+    FmatSlots<N> s = tslots<N, FmatSlots<N>::NMv, FmatSlots<N>::NVv>(dyn);
+    const InstWs ws = inst_ws(I);
+    const CstW cl = cst_layout(n, m, p);
+    double *PA = s.m[0], *PC = s.m[1], *PJ = s.m[2], *F = s.m[3], *G = s.m[4], *Js = s.m[5];
+    double *Pb = s.v[0], *Pe = s.v[1], *cc = s.v[2], *ek = s.v[3];
+    tload<N>(n, m, ws.cst + cl.G, m, G, lane);
+    tload<N>(n, n, ws.cst + cl.J, n, Js, lane);
+    tload<N>(n, n, I.F, n, F, lane);
+    if (lane < N) {
+        cc[lane] = 0.0;
+        ek[lane] = 0.0;
+        Pb[lane] = 0.0;
+        Pe[lane] = 0.0;
+    }
+    wsync();
+    tcopy<N>(F, PA, lane);
+    tgemm<N, false, true, true>(G, G, PC, 1.0, 0.0, lane);
+    tcopy<N>(Js, PJ, lane);
+    const int64_t nn = (int64_t)n * n;
+#pragma unroll 1
+    for (int j = 1; j < I.B; ++j)
+        t_step_combine<N>(m, F, cc, G, ek, Js, PA, Pb, PC, Pe, PJ, s, lane, n, ws.ops + (int64_t)(j - 1) * 2 * nn);
+    double* out = ws.agg;
+    tstore<N>(n, n, PA, out, n, lane);
+    tstore<N>(n, n, PC, out + nn + n, n, lane);
+    tstore<N>(n, n, PJ, out + 2 * nn + 2 * n, n, lane);
+}
+
+// Vector part of a full chunk's element for an instance with opf set: the
+// matrix part is the common one (t_fmat); eta and b by the stored operators,
+// eta' = E_j eta + W r_k, b' = b + B^_j eta, with the operator rows and the
+// reference of the next step loaded one step ahead.
+template <int N>
+WDI void t_fold_vec(const GInst& I, const InstWs& ws, int64_t c, int64_t k1, const double* W, double* Pb, double* Pe,
+                    double* rk, int lane) {
+    constexpr int ld = TL<N>::ld;
+    const int n = I.n, p = I.p;
+    const int64_t nn = (int64_t)n * n, ED = elem_doubles(n);
+    const double* src = ws.agg;
+    double* out = ws.agg + c * ED;
+    for (int64_t idx = lane; idx < nn; idx += kW) {
+        out[idx] = src[idx];
+        out[nn + n + idx] = src[nn + n + idx];
+        out[2 * nn + 2 * n + idx] = src[2 * nn + 2 * n + idx];
+    }
+    // eta = W r_{k1-1}, b = 0
+    if (lane < N) rk[lane] = lane < p ? I.r[(k1 - 1) * p + lane] : 0.0;
+    wsync();
+    if (lane < N) {
+        double e = 0.0;
+        for (int q = 0; q < p; ++q) e = fma(W[lane * ld + q], rk[q], e);
+        Pe[lane] = lane < n ? e : 0.0;
+        Pb[lane] = 0.0;
+    }
+    wsync();
+    double Er[N], Br[N], rr = 0.0;
+    auto fetch = [&](int j) {
+        if (j < I.B) {
+            const double* E = ws.ops + (int64_t)(j - 1) * 2 * nn + (int64_t)lane * n;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                Er[l] = (lane < n && l < n) ? E[l] : 0.0;
+                Br[l] = (lane < n && l < n) ? E[nn + l] : 0.0;
+            }
+            rr = lane < p ? I.r[(k1 - 1 - j) * p + lane] : 0.0;
+        }
+    };
+    fetch(1);
+#pragma unroll 1
+    for (int j = 1; j < I.B; ++j) {
+        double Ej[N], Bj[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            Ej[l] = Er[l];
+            Bj[l] = Br[l];
+        }
+        if (lane < N) rk[lane] = rr;
+        fetch(j + 1);
+        wsync();
+        double nb = 0.0, ne = 0.0;
+        if (lane < N) {
+            nb = Pb[lane];
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                nb = fma(Bj[l], Pe[l], nb);
+                ne = fma(Ej[l], Pe[l], ne);
+            }
+            for (int q = 0; q < p; ++q) ne = fma(W[lane * ld + q], rk[q], ne);
+        }
+        wsync();
+        if (lane < N) {
+            Pb[lane] = nb;
+            Pe[lane] = ne;
+        }
+        wsync();
+    }
+    if (lane < n) {
+        out[nn + lane] = Pb[lane];
+        out[2 * nn + n + lane] = Pe[lane];
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(kW) void t_fold(const GInst* inst, int ninst, int64_t nchunks) {
     extern __shared__ __align__(16) double dyn[];
@@ -815,6 +959,12 @@ __global__ __launch_bounds__(kW) void t_fold(const GInst* inst, int ninst, int64
         tload<N>(n, m, ws.cst + cl.G, m, G, lane);
         tload<N>(n, n, ws.cst + cl.J, n, Js, lane);
         tload<N>(n, p, ws.cst + cl.W, p, W, lane);
+    }
+    if constexpr (N == 8) {
+        if (I.opf && k1 - k0 == I.B) {
+            t_fold_vec<N>(I, ws, c, k1, W, Pb, Pe, rk, lane);
+            return;
+        }
     }
     auto step_data = [&](int64_t k, bool first) {
         if (first || (ps & kPS_F)) tload<N>(n, n, step_ptr(I.F, ps, kPS_F, k, (int64_t)n * n), n, F, lane);
@@ -1368,36 +1518,40 @@ template <int N>
 struct TileNames;
 template <>
 struct TileNames<8> {
-    static constexpr const char* n[9] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll",
-                                          "t8_tree", "t8_tanchor", "t8_ftree"};
+    static constexpr const char* n[10] = {"t8_prep", "t8_fold", "t8_chain", "t8_final", "t8_fchain", "t8_roll",
+                                          "t8_tree", "t8_tanchor", "t8_ftree", "t8_fmat"};
 };
 template <>
 struct TileNames<16> {
-    static constexpr const char* n[9] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll",
-                                          "t16_tree", "t16_tanchor", "t16_ftree"};
+    static constexpr const char* n[10] = {"t16_prep", "t16_fold", "t16_chain", "t16_final", "t16_fchain", "t16_roll",
+                                          "t16_tree", "t16_tanchor", "t16_ftree", "t16_fmat"};
 };
 template <>
 struct TileNames<32> {
-    static constexpr const char* n[9] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll",
-                                          "t32_tree", "t32_tanchor", "t32_ftree"};
+    static constexpr const char* n[10] = {"t32_prep", "t32_fold", "t32_chain", "t32_final", "t32_fchain", "t32_roll",
+                                          "t32_tree", "t32_tanchor", "t32_ftree", "t32_fmat"};
 };
 
 template <int N, typename OT>
 static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, hipStream_t s,
-                     const StageHook* h) {
+                     const StageHook* h, bool opf_any) {
     const char* const* nm = TileNames<N>::n;
     const size_t glds = wave_lds_bytes(N);
     static bool attr = false;
     if (!attr) {
         const void* ks[] = {(const void*)t_fold<N>, (const void*)t_chain<N>, (const void*)t_final<N, OT>,
                             (const void*)t_roll<N, OT>, (const void*)g_prep, (const void*)t_tlevel<N>,
-                            (const void*)t_tanchor<N>, (const void*)t_ftlevel<N>};
+                            (const void*)t_tanchor<N>, (const void*)t_ftlevel<N>, (const void*)t_fmat<N>};
         for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
     {
         WStage st(h, nm[0], s);
         g_prep<<<ninst, kW, glds, s>>>(d_inst, ninst, N);
+    }
+    if (N == 8 && opf_any) {
+        WStage st(h, nm[9], s);
+        t_fmat<N><<<ninst, kW, FmatSlots<N>::bytes(), s>>>(d_inst, ninst);
     }
     {
         WStage st(h, nm[1], s);
@@ -1440,20 +1594,20 @@ static void run_tile(const GInst* d_inst, int ninst, int64_t nchunks, int64_t tr
 
 template <typename OT>
 static hipError_t tile_typed(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd,
-                             hipStream_t s, const StageHook* h) {
+                             hipStream_t s, const StageHook* h, bool opf_any) {
     switch (N) {
-        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
-        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
-        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h); break;
+        case 8: run_tile<8, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h, opf_any); break;
+        case 16: run_tile<16, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h, opf_any); break;
+        case 32: run_tile<32, OT>(d_inst, ninst, nchunks, tree_nc, want_fwd, s, h, opf_any); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t tile_solve(int N, const GInst* d_inst, int ninst, int64_t nchunks, int64_t tree_nc, bool want_fwd, bool f32,
-                      hipStream_t s, const StageHook* h) {
-    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h)
-               : tile_typed<double>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h);
+                      hipStream_t s, const StageHook* h, bool opf_any) {
+    return f32 ? tile_typed<float>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h, opf_any)
+               : tile_typed<double>(N, d_inst, ninst, nchunks, tree_nc, want_fwd, s, h, opf_any);
 }
 
 }  // namespace lqt

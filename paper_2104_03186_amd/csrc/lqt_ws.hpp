@@ -94,6 +94,13 @@ __host__ __device__ inline int64_t ws_cst_doubles(int n, int m, int p, int eng) 
 __host__ __device__ inline bool ws_op_form(int eng, bool has_c) { return eng != 0 && !has_c; }
 __host__ __device__ inline int64_t ws_ops_doubles(int d, int64_t B) { return (B > 1 ? B - 1 : 0) * 2 * (int64_t)d * d; }
 __host__ __device__ inline int64_t ws_opr_doubles(int d, int64_t B, int p) { return 2 * (int64_t)d * B * p; }
+// Doubles of ops (and opr) of an instance: the workgroup engines' operator
+// form, or the wavefront engine's (opf: ops only, the vector recursion runs
+// per chunk with them).
+__host__ __device__ inline int64_t ws_op_doubles(int eng, bool has_c, bool opf, int d, int64_t B, int p) {
+    if (eng != 0) return ws_op_form(eng, has_c) ? ws_ops_doubles(d, B) + ws_opr_doubles(d, B, p) : 0;
+    return opf ? ws_ops_doubles(d, B) : 0;
+}
 
 // Chunk scans of an instance as trees (either chunked engine; GInst::tree):
 // the value at the chunk starts by recursive doubling over the chunk elements
@@ -108,9 +115,9 @@ constexpr int64_t kTreeMinNC = 128;
 //     affine maps) | xs[NC] (state at chunk starts) | ops | opr (operator form)
 //     | tree[2][NC] (chunk elements or chunk maps of the tree levels)
 __host__ __device__ inline int64_t ws_doubles(int n, int m, int p, int eng, int64_t NC, int64_t B = 0,
-                                              bool has_c = true, bool tree_scan = false) {
+                                              bool has_c = true, bool tree_scan = false, bool opf = false) {
     const int d = ws_dim(n, eng);
-    const int64_t ops = ws_op_form(eng, has_c) ? ws_ops_doubles(d, B) + ws_opr_doubles(d, B, p) : 0;
+    const int64_t ops = ws_op_doubles(eng, has_c, opf, d, B, p);
     const int64_t tree = tree_scan ? 2 * NC * elem_doubles(d) : 0;
     return ws_cst_doubles(n, m, p, eng) + NC * elem_doubles(d) + (NC + 1) * val_doubles(d) + NC * val_doubles(d) +
            NC * d + ops + tree + 32;
@@ -132,7 +139,7 @@ __device__ inline InstWs inst_ws(const GInst& I) {
     w.xs = w.map + I.NC * val_doubles(d);
     w.ops = w.xs + I.NC * d;
     w.opr = w.ops + ws_ops_doubles(d, I.B);
-    w.tree = w.ops + (ws_op_form(I.eng, I.c != nullptr) ? ws_ops_doubles(d, I.B) + ws_opr_doubles(d, I.B, I.p) : 0);
+    w.tree = w.ops + ws_op_doubles(I.eng, I.c != nullptr, I.opf != 0, d, I.B, I.p);
     return w;
 }
 

@@ -241,3 +241,26 @@ def test_routing_tree_field_validation(api):
         check(do.host(), oracle.solve(prob), TOL["fp64"])
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("T", [16 * 5, 16 * 9 + 7, 16 * 130 + 3])
+def test_wave8_operator_form_fold(api, prec, T):
+    """Class-8 time-invariant instances without offsets (the operator form of
+    the wavefront engine's fold: one matrix fold per instance, the vector
+    recursion per chunk), full and ragged last chunks, chains and trees, and
+    one alone against the same instance in a batch."""
+    probs = [inputs.diag_problem(8, 4, T, 2, 5), inputs.random_problem(7, 3, T, seed=97, with_c=False, scale=0.95),
+             inputs.diag_problem(6, 3, T + 33, 2, 6)]
+    _say("wave8 operator form", prec, "T=", T)
+    mix = solve(api, probs, prec=prec)
+    for i, p in enumerate(probs):
+        assert mix[i][0] == 0, i
+        check(mix[i][1], oracle.solve(p), TOL[prec])
+    (alone,) = solve(api, [probs[1]], prec=prec)
+    for f in FAMILIES:
+        assert np.array_equal(mix[1][1][f], alone[1][f]), f
+    for tree in (True, False):
+        (res,) = solve(api, [probs[0]], prec=prec, chunk=0, tree=tree)
+        assert res[0] == 0
+        check(res[1], oracle.solve(probs[0]), TOL[prec])
