@@ -5,8 +5,9 @@ instance, each compared with lqt_solve of the same instance (the same
 kernels and chunking: equal bit for bit) and with the oracle (the FP64 gate
 of the parity tests); a generalised-cost instance, a wavefront-engine
 instance, a long instance whose chunk elements are scanned as a tree, both
-chunked engines with the chunk scans as trees by request, and a MIXED plan;
-the size limit of the static workspace.
+chunked engines with the chunk scans as trees by request, the operator form
+of the fold on both chunked engines, and a MIXED plan; the size limit of the
+static workspace.
 """
 import sys
 
@@ -106,6 +107,27 @@ def test_forced_trees(api):
         plan.set_routing(tree=True)
         for prob in (inputs.diag_problem(16, 8, 2000, 2, 7), inputs.random_problem(6, 3, 3001, seed=13)):
             _say("noalloc with trees", prob.n, prob.m, prob.T)
+            got, alone = both(api, plan, prob, torch.float64)
+            check(got, alone, oracle.solve(prob), TOL["fp64"])
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("tree", [None, True])
+def test_operator_form_fold(api, tree):
+    """Time-invariant instances without offsets: the operator form of the
+    fold (one matrix fold per instance, then the vector recursion per chunk)
+    on the wavefront engine (class 8) and the workgroup engine (class 16),
+    chains and trees, the same with and without allocation."""
+    import torch
+
+    plan = api.Plan(16, 8, prec="fp64")
+    try:
+        plan.set_routing(tree=tree)
+        for prob in (inputs.diag_problem(8, 4, 2000, 2, 5), inputs.random_problem(7, 3, 1500, seed=97, with_c=False,
+                                                                                  scale=0.95),
+                     inputs.diag_problem(16, 8, 2500, 2, 6)):
+            _say("noalloc operator-form fold", prob.n, prob.m, prob.T, "tree", tree)
             got, alone = both(api, plan, prob, torch.float64)
             check(got, alone, oracle.solve(prob), TOL["fp64"])
     finally:
