@@ -1448,6 +1448,12 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
     const OT* const iD = (const OT*)I.d;
     OT* const oX = (OT*)I.x;
     OT* const oU = (OT*)I.u;
+    // every lane takes part: G consecutive lanes share a row of K (u = d - K x)
+    // and of [F L] (x' = F x + L u + c), each summing every G-th term, then a
+    // butterfly over the group
+    constexpr int G = kW / N;
+    static_assert((G & (G - 1)) == 0, "row groups of a power of two lanes");
+    const int r = lane / G, g = lane % G;
     tvec_load<N>(n, ws.xs + c * n, x, lane);
     double fin = 0.0;
 #pragma unroll 1
@@ -1459,25 +1465,28 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
             if (lane < N) cc[lane] = (I.c && lane < n) ? step_ptr(I.c, ps, kPS_c, k, n)[lane] : 0.0;
             wsync();
         }
-        if (lane < N) {
+        {
             double a = 0.0;
-            if (lane < m) {
-                const OT* Kk = iK + k * m * n;
-                a = (double)iD[k * m + lane];
-                for (int j = 0; j < n; ++j) a = fma(-(double)Kk[lane * n + j], x[j], a);
+            if (r < m) {
+                const OT* Kr = iK + k * m * n + (int64_t)r * n;
+                for (int j = g; j < n; j += G) a = fma(-(double)Kr[j], x[j], a);
             }
-            u[lane] = a;
+#pragma unroll
+            for (int o = G / 2; o >= 1; o >>= 1) a += __shfl_xor(a, o, G);
+            if (g == 0) u[r] = r < m ? (double)iD[k * m + r] + a : 0.0;
         }
         wsync();
         if (oX && lane < n) oX[k * n + lane] = (OT)x[lane];
         if (oU && lane < m) oU[k * m + lane] = (OT)u[lane];
-        if (lane < N) {
-            double a = cc[lane];
+        {
+            double a = 0.0;
 #pragma unroll
-            for (int q = 0; q < N; ++q) a = fma(F[lane * ld + q], x[q], a);
+            for (int q = g; q < N; q += G) a = fma(F[r * ld + q], x[q], a);
 #pragma unroll
-            for (int q = 0; q < N; ++q) a = fma(L[lane * ld + q], u[q], a);
-            t[lane] = a;
+            for (int q = g; q < N; q += G) a = fma(L[r * ld + q], u[q], a);
+#pragma unroll
+            for (int o = G / 2; o >= 1; o >>= 1) a += __shfl_xor(a, o, G);
+            if (g == 0) t[r] = cc[r] + a;
         }
         wsync();
         if (lane < N) {
