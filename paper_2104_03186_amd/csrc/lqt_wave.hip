@@ -1481,9 +1481,9 @@ __global__ __launch_bounds__(kW) void t_roll(const GInst* inst, int ninst, int64
         {
             double a = 0.0;
 #pragma unroll
-            for (int q = g; q < N; q += G) a = fma(F[r * ld + q], x[q], a);
+            for (int i = 0; i < N / G; ++i) a = fma(F[r * ld + g + i * G], x[g + i * G], a);
 #pragma unroll
-            for (int q = g; q < N; q += G) a = fma(L[r * ld + q], u[q], a);
+            for (int i = 0; i < N / G; ++i) a = fma(L[r * ld + g + i * G], u[g + i * G], a);
 #pragma unroll
             for (int o = G / 2; o >= 1; o >>= 1) a += __shfl_xor(a, o, G);
             if (g == 0) t[r] = cc[r] + a;
